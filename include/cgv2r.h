@@ -1,0 +1,229 @@
+/* cgv2r.h -- C ABI of an MI355X (gfx950) differentiable 2D-Gaussian surfel tile rasterizer.
+ *
+ * The operations follow CityGaussianV2 (arXiv 2411.00771):
+ *   - surfels {mu, tangents t_u, t_v, scales (s_u, s_v), opacity, SH features} of the 2DGS
+ *     model (Sec. 3.1, "2D Gaussian Splatting" paragraph);
+ *   - colour by front-to-back alpha blending (Sec. 3.1, Eq. 1), plus the depth (Sec. 3.2;
+ *     median depth, Sec. 5.1) and normal (Sec. 3.1) renders the losses need;
+ *   - the decomposed (SSIM-only) densification gradient (Sec. 3.2, Eq. 2) and the
+ *     elongation rate eta = min(s_u, s_v) / max(s_u, s_v) (Sec. 3.2).
+ *
+ * Conventions shared by every call
+ *   - Array pointers are DEVICE pointers owned by the caller, contiguous, 16-byte aligned
+ *     (256-byte recommended).  Structs themselves live in host memory and are read during
+ *     the call only.  Layouts are planar: field[c][n] for per-surfel data, [V][c][H][W] for
+ *     images.
+ *   - Every call enqueues work on the given HIP stream (NULL = the null stream) and returns
+ *     without synchronising.  The library never allocates device memory, never prints and
+ *     never aborts.  It holds no state besides a thread-local last-HIP-error code.
+ *   - Return value: CGV2_OK or a negative CGV2_E* code.  On an error nothing was enqueued
+ *     (CGV2_EHIP: a launch failed; cgv2_last_hip_error() gives the hipError_t).
+ *   - Conditions found on the device (intersection overflow) are reported through device
+ *     words, never through return codes.
+ *   - The V cameras of one call must share width and height.
+ *   - Pixel (i, j) is sampled at (i + 0.5, j + 0.5).  Tiles are 16 x 16 pixels, numbered
+ *     row-major per view: tile = ty * tiles_x + tx.
+ */
+#ifndef CGV2R_H
+#define CGV2R_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGV2_OK 0
+#define CGV2_EINVAL (-1)      /* null pointer, n < 0, V < 1, sh_degree outside 0..3, W/H <= 0,
+                                 more than 65535 tiles per axis, mismatched camera sizes */
+#define CGV2_EWORKSPACE (-2)  /* workspace smaller than the matching *_workspace() size */
+#define CGV2_EUNSUPPORTED (-3)/* no usable gfx950 device */
+#define CGV2_EHIP (-4)        /* a HIP launch failed */
+
+#define CGV2_TILE 16
+#define CGV2_REC_FLOATS 20    /* floats per render record, see cgv2_proj */
+
+/* project flags (cgv2_proj.flags) */
+#define CGV2_F_VISIBLE 1u     /* tile rect non-empty: the surfel is binned in this view */
+#define CGV2_F_NEAR 2u        /* centre depth <= znear */
+#define CGV2_F_OPACITY 4u     /* opacity <= 1/255: alpha can never reach the 1/255 skip level */
+#define CGV2_F_BEHIND 8u      /* the cutoff disc is not entirely in front of the camera */
+#define CGV2_F_NONFINITE 16u  /* NaN/Inf parameter */
+#define CGV2_F_LOWPASS 32u    /* the screen low-pass filter wins at the sample nearest the centre
+                                 (the sub-pixel case of Sec. 3.2) */
+
+/* Pinhole camera.  World -> camera: Xc = R Xw + t (row-major R; x right, y down, z forward). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9], t[3];
+  float znear;   /* surfels whose centre depth <= znear are culled */
+  float bg[3];   /* background colour added with the final transmittance */
+} cgv2_camera;
+
+/* Surfel parameters (Sec. 3.1): n surfels, planar SoA float32.
+ *   mean[3][n]; log_scale[2][n] (s = exp); quat[4][n] (w, x, y, z; normalised inside; the
+ *   rotation's columns are t_u, t_v and the surfel normal); opacity_logit[n] (sigmoid);
+ *   sh[(deg+1)^2][3][n] real SH coefficients, index l*l + l + m, colour =
+ *   max(0, 0.5 + sum f Y) with the Condon-Shortley phase (Y_1^1 = -sqrt(3/4pi) x). */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  const float *mean, *log_scale, *quat, *opacity_logit, *sh;
+} cgv2_surfels;
+
+/* Per-view projection.  rec[V][n][20] is written for visible surfels only:
+ *   0,1  cx_hi, cy_hi   integer part of the projected centre (pixels)
+ *   2,3  cx_lo, cy_lo   remainder: centre = hi + lo
+ *   4-7  a11 a12 a21 a22  with x' = x - cx, y' = y - cy the ray through (x, y) meets the surfel
+ *   8-10 w0 w1 w2        plane at local (u, v) = (a11 x' + a12 y', a21 x' + a22 y') / w,
+ *                        w = w0 + w1 x' + w2 y' (the inverse homography, scaled to max |coef| = 1)
+ *   11   z_c            centre depth (sort key); intersection depth = z_c w0 / w
+ *   12   opacity        13-15 rgb   16-18 camera-space normal (facing the camera)   19 k^2 cutoff
+ * rect[V][n][4] = tx0, ty0, tx1, ty1 (end exclusive; all 0 when not visible); radius[V][n] screen
+ * radius in pixels; flags[V][n] CGV2_F_* bits (written for every surfel). */
+typedef struct {
+  float* rec;
+  uint16_t* rect;
+  float* radius;
+  uint8_t* flags;
+} cgv2_proj;
+
+/* Tile bins.  ranges[V * tiles + 1]: list of tile t in view v is ids[ranges[v*tiles + t] ..
+ * ranges[v*tiles + t + 1]), ordered front to back by (float32 bits of z_c, id).
+ * *status is set to 1 when the intersections exceed 'capacity' (sticky: the library never
+ * clears it; the caller zeroes it before the first call).  *needed receives the total number
+ * of intersections of the call.  While *status != 0, bins are invalid, render calls write
+ * nothing and the caller must rerun with capacity >= *needed. */
+typedef struct {
+  int64_t capacity;  /* entries in ids (< 2^32 - 1) */
+  uint32_t* ids;
+  uint32_t* ranges;
+  int32_t* status;
+  int64_t* needed;
+} cgv2_bins;
+
+/* Rendered images [V][c][H][W] and the backward checkpoint.  rgb (Eq. 1, with T_final * bg),
+ * depth = sum w z (not normalised), depth_med (depth of the last fragment whose incoming
+ * transmittance exceeds 0.5; 0 if none), normal = sum w n (not normalised), alpha = 1 - T_final.
+ * Checkpoint: T_final; last = one past the last contributing list entry; med = list index of
+ * the median fragment (0xffffffff if none).  rgb/depth/depth_med/normal/alpha may be NULL;
+ * T_final/last/med may be NULL when no backward pass follows. */
+typedef struct {
+  float *rgb, *depth, *depth_med, *normal, *alpha, *T_final;
+  uint32_t *last, *med;
+} cgv2_image;
+
+/* Upstream gradients [V][c][H][W]; any may be NULL (= zero).  d_rgb_ssim is the part of d_rgb
+ * that comes from the SSIM term (the DGD source of Eq. 2); NULL gives g_view_ssim = 0. */
+typedef struct {
+  const float *d_rgb, *d_depth, *d_depth_med, *d_normal, *d_alpha;
+  const float* d_rgb_ssim;
+} cgv2_image_grad;
+
+/* Parameter gradients accumulate (+=) over views and calls: the caller zeroes them.
+ * g_view_total / g_view_ssim [V][2][n] are overwritten: the gradient w.r.t. a rigid screen
+ * translation of the surfel's image (the 2DGS form of the view-space position gradient of
+ * Sec. 3.1), in NDC units (pixels * (W/2, H/2)), zero for surfels not visible in the view. */
+typedef struct {
+  float *d_mean, *d_log_scale, *d_quat, *d_opacity_logit, *d_sh;
+  float *g_view_total, *g_view_ssim;
+} cgv2_grads;
+
+/* Densification parameters: omega of Eq. 2 (0.9 in Sec. 5.1), elongation threshold eta_min
+ * (Sec. 3.2 leaves it open; 0.05 suggested), clone/split threshold on the accumulated
+ * average DGD gradient (NDC units). */
+typedef struct {
+  float omega, eta_min, grad_threshold;
+} cgv2_densify_params;
+
+/* Densification state [n], accumulated across calls until the caller resets it.
+ * mask bits: 1 high gradient, 2 elongated (eta < eta_min), 4 clone/split candidate
+ * (high and not elongated), 8 low-pass dominant in a view of this call.
+ * counters[8] (overwritten): visible (summed over views), high, elongated, high & elongated,
+ * low-pass & visible (summed over views), candidates, 0, 0.  scale[V]: the Eq. 2 factor used
+ * for each view. */
+typedef struct {
+  float *accum_dgd, *accum_total, *max_radius;
+  int32_t* denom;
+  uint8_t* mask;
+  uint32_t* counters;
+  float* scale;
+} cgv2_densify_state;
+
+/* Per-surfel projection of n surfels into V views (2DGS surfel model, Sec. 3.1).  Computes the
+ * screen transform M = K [R s_u t_u | R s_v t_v | R mu + t] in FP64, SH colour, the normal
+ * flipped to face the camera, sigmoid opacity, the cutoff k^2 = 2 ln(255 o) at which alpha
+ * reaches 1/255, and the tile rect of the exact conic bound of the k-disc united with the
+ * low-pass filter disc of radius k sqrt(2)/2 px (Sec. 3.2).
+ * Errors: CGV2_EINVAL (nulls, bad sizes), CGV2_EHIP. */
+int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* hip_stream);
+
+/* Workspace bytes for cgv2_bin_sort with the given capacity, view count and tiles per view. */
+size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view);
+
+/* Tile binning: counts intersections per tile, prefix-sums them into ranges, scatters
+ * (depth bits, id) keys and sorts every tile's list; depth ties are broken by id, so the order
+ * is deterministic and bit-exact.  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_bin_sort(const cgv2_proj* proj, const cgv2_camera* cams, int32_t V, int64_t n, cgv2_bins* bins,
+                  void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Forward render (Sec. 3.1, Eq. 1): per pixel, front to back over its tile list,
+ * alpha = min(0.99, o exp(-rho/2)) with rho = min(rho_3d, rho_2d) (ray-splat intersection vs
+ * screen low-pass filter), entries with alpha < 1/255 skipped, stop before T(1 - alpha) < 1e-4.
+ * Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_render_fwd(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                    cgv2_image* img, void* hip_stream);
+
+/* Workspace bytes for cgv2_loss. */
+size_t cgv2_loss_workspace(int32_t width, int32_t height, int32_t V);
+
+/* Photometric loss of Sec. 3.1: L = (1 - lambda) mean|I - I*| + lambda (1 - SSIM(I, I*)), SSIM with
+ * an 11x11 Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, zero padding, mean over pixels and
+ * channels.  img, target: [V][3][H][W].  Writes d_img = dL/dI, d_img_ssim = d(lambda (1 - SSIM))/dI,
+ * and loss[V][3] = {L, mean L1, SSIM}.  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_loss(const float* img, const float* target, int32_t V, int32_t width, int32_t height, float lambda,
+              float* d_img, float* d_img_ssim, float* loss, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes for cgv2_render_bwd. */
+size_t cgv2_render_bwd_workspace(int64_t n, int32_t V);
+
+/* Backward of project + render_fwd.  Traverses each pixel's list in reverse from the checkpoint
+ * (T recovered as T_{i+1} / (1 - alpha_i); no per-fragment state is stored), reduces the per-surfel
+ * gradients of every tile in registers and adds them atomically, then chains them to the
+ * parameters.  Also writes the total and SSIM-only view-space gradients (Eq. 2's inputs).
+ * img must hold T_final, last and med of the matching cgv2_render_fwd call.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams,
+                    int32_t V, const cgv2_image* img, const cgv2_image_grad* up, cgv2_grads* grads,
+                    void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes for cgv2_densify_stats. */
+size_t cgv2_densify_workspace(int64_t n, int32_t V);
+
+/* Densification statistics (Sec. 3.2): per view, the DGD factor of Eq. 2,
+ * scale = max(omega * sum_vis |g_total| / sum_vis |g_ssim|, 1) (both sums over the surfels visible in
+ * the view, so the ratio equals the ratio of the two averages; scale = 1 if the SSIM sum is 0), reduced
+ * in a fixed order (deterministic); then accum_dgd += scale |g_ssim|, accum_total += |g_total|,
+ * denom += 1, max_radius = max(max_radius, radius) over visible surfels; eta, masks and counters.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* grads, int32_t V,
+                       const cgv2_densify_params* prm, cgv2_densify_state* st, void* workspace, size_t ws_bytes,
+                       void* hip_stream);
+
+/* Counting variant of cgv2_render_fwd for work accounting: counters[3] (device, uint64, added to)
+ * receive the (pixel, entry) pairs the forward evaluates, the pairs that contribute, and the pairs
+ * the reverse pass walks (entries before each pixel's 'last').  Same rules as the render; writes no
+ * image.  Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_render_count(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V,
+                      int64_t n, uint64_t* counters, void* hip_stream);
+
+/* Error string for a CGV2_E* code; thread-local hipError_t of the last failing launch. */
+const char* cgv2_strerror(int code);
+int cgv2_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGV2R_H */

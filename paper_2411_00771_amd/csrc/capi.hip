@@ -1,0 +1,191 @@
+// C ABI of the surfel rasterizer: argument validation, workspace sizing, camera packing and the
+// launch sequence of each call.  Nothing here allocates, prints or synchronises.
+#include <string.h>
+
+#include "cgv2r_device.h"
+#include "cgv2r_kernels.h"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return CGV2_OK;
+  g_last_hip = (int)e;
+  return CGV2_EHIP;
+}
+
+bool cams_ok(const cgv2_camera* c, int32_t V) {
+  if (!c || V < 1) return false;
+  for (int v = 0; v < V; ++v) {
+    if (c[v].width <= 0 || c[v].height <= 0) return false;
+    if (c[v].width != c[0].width || c[v].height != c[0].height) return false;
+    if ((c[v].width + CGV2_TILE - 1) / CGV2_TILE > 65535 || (c[v].height + CGV2_TILE - 1) / CGV2_TILE > 65535)
+      return false;
+  }
+  return true;
+}
+
+bool surfels_ok(const cgv2_surfels* s) {
+  return s && s->n >= 0 && s->n < (int64_t)0xffffffff && s->sh_degree >= 0 && s->sh_degree <= 3 &&
+         (s->n == 0 || (s->mean && s->log_scale && s->quat && s->opacity_logit && s->sh));
+}
+
+bool proj_ok(const cgv2_proj* p) { return p && p->rec && p->rect && p->radius && p->flags; }
+
+bool bins_ok(const cgv2_bins* b) {
+  return b && b->capacity >= 0 && b->capacity < (int64_t)0xffffffff && b->ranges && b->status && b->needed &&
+         (b->capacity == 0 || b->ids);
+}
+
+cgv2::CamPack pack(const cgv2_camera* c, int v0, int count) {
+  cgv2::CamPack p;
+  memset(&p, 0, sizeof(p));
+  for (int k = 0; k < count; ++k) {
+    const cgv2_camera& s = c[v0 + k];
+    cgv2::DevCam& d = p.c[k];
+    d.W = s.width; d.H = s.height;
+    d.fx = s.fx; d.fy = s.fy; d.cx = s.cx; d.cy = s.cy;
+    memcpy(d.R, s.R, sizeof(d.R));
+    memcpy(d.t, s.t, sizeof(d.t));
+    d.znear = s.znear;
+    memcpy(d.bg, s.bg, sizeof(d.bg));
+  }
+  p.v0 = v0;
+  p.count = count;
+  return p;
+}
+
+inline int tiles_x(const cgv2_camera* c) { return (c[0].width + CGV2_TILE - 1) / CGV2_TILE; }
+inline int tiles_y(const cgv2_camera* c) { return (c[0].height + CGV2_TILE - 1) / CGV2_TILE; }
+
+}  // namespace
+
+extern "C" {
+
+const char* cgv2_strerror(int code) {
+  switch (code) {
+    case CGV2_OK: return "ok";
+    case CGV2_EINVAL: return "invalid argument";
+    case CGV2_EWORKSPACE: return "workspace too small";
+    case CGV2_EUNSUPPORTED: return "unsupported device";
+    case CGV2_EHIP: return "HIP launch failed";
+    default: return "unknown error";
+  }
+}
+
+int cgv2_last_hip_error(void) { return g_last_hip; }
+
+int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* stream) {
+  if (!surfels_ok(s) || !cams_ok(cams, V) || !proj_ok(proj)) return CGV2_EINVAL;
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_project(*s, pack(cams, v0, cnt), *proj, (hipStream_t)stream));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view) {
+  if (capacity < 0 || V < 1 || tiles_per_view < 1) return 0;
+  size_t off[7];
+  return cgv2_binsort_ws_layout(capacity, V, tiles_per_view, off);
+}
+
+int cgv2_bin_sort(const cgv2_proj* proj, const cgv2_camera* cams, int32_t V, int64_t n, cgv2_bins* bins,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  if (!cams_ok(cams, V) || !proj || !proj->rect || !proj->rec || !bins_ok(bins) || n < 0 || !workspace)
+    return CGV2_EINVAL;
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  if ((int64_t)V * tx * ty >= (int64_t)0x7fffffff) return CGV2_EINVAL;
+  if (ws_bytes < cgv2_bin_sort_workspace(bins->capacity, V, tx * ty)) return CGV2_EWORKSPACE;
+  return hip_status(cgv2_launch_bin_sort(*proj, n, V, tx, ty, *bins, workspace, (hipStream_t)stream));
+}
+
+int cgv2_render_fwd(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                    cgv2_image* img, void* stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !img || n < 0) return CGV2_EINVAL;
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_render_fwd(*proj, *bins, pack(cams, v0, cnt), n, tx, ty, *img,
+                                                     (hipStream_t)stream));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+int cgv2_render_count(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                      uint64_t* counters, void* stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !counters || n < 0) return CGV2_EINVAL;
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_render_count(*proj, *bins, pack(cams, v0, cnt), n, tx, ty,
+                                                       (unsigned long long*)counters, (hipStream_t)stream));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+size_t cgv2_loss_workspace(int32_t width, int32_t height, int32_t V) {
+  if (width <= 0 || height <= 0 || V < 1) return 0;
+  size_t off[2];
+  return cgv2_loss_ws_layout(width, height, V, off);
+}
+
+int cgv2_loss(const float* img, const float* target, int32_t V, int32_t width, int32_t height, float lambda,
+              float* d_img, float* d_img_ssim, float* loss, void* workspace, size_t ws_bytes, void* stream) {
+  if (!img || !target || !d_img || !d_img_ssim || !loss || !workspace || V < 1 || width <= 0 || height <= 0)
+    return CGV2_EINVAL;
+  if ((int64_t)V * 3 > 65535) return CGV2_EINVAL;
+  if (ws_bytes < cgv2_loss_workspace(width, height, V)) return CGV2_EWORKSPACE;
+  return hip_status(
+      cgv2_launch_loss(img, target, V, width, height, lambda, d_img, d_img_ssim, loss, workspace, (hipStream_t)stream));
+}
+
+size_t cgv2_render_bwd_workspace(int64_t n, int32_t V) {
+  if (n < 0 || V < 1) return 0;
+  return ((size_t)cgv2::kGradFields * sizeof(float) * (size_t)n * (size_t)V + 255) & ~(size_t)255;
+}
+
+int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams,
+                    int32_t V, const cgv2_image* img, const cgv2_image_grad* up, cgv2_grads* g, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  if (!surfels_ok(s) || !proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !img || !up || !g) return CGV2_EINVAL;
+  if (!img->T_final || !img->last || !img->med) return CGV2_EINVAL;
+  if (s->n > 0 && (!g->d_mean || !g->d_log_scale || !g->d_quat || !g->d_opacity_logit || !g->d_sh))
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_render_bwd_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  float* rg = (float*)workspace;
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    int rc = hip_status(cgv2_launch_render_bwd(*proj, *bins, pack(cams, v0, cnt), s->n, tx, ty, *img, *up, rg,
+                                               (hipStream_t)stream));
+    if (rc) return rc;
+    rc = hip_status(cgv2_launch_project_bwd(*s, pack(cams, v0, cnt), proj->flags, rg, *g, (hipStream_t)stream));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+size_t cgv2_densify_workspace(int64_t n, int32_t V) {
+  if (n < 0 || V < 1) return 0;
+  size_t off[1];
+  return cgv2_densify_ws_layout(n, V, off);
+}
+
+int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* g, int32_t V,
+                       const cgv2_densify_params* prm, cgv2_densify_state* st, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  if (!surfels_ok(s) || !proj || !proj->flags || !proj->radius || !g || !g->g_view_total || !prm || !st ||
+      V < 1 || V > 64)
+    return CGV2_EINVAL;
+  if (!st->accum_dgd || !st->accum_total || !st->max_radius || !st->denom || !st->mask || !st->counters)
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_densify_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_densify(*s, *proj, *g, V, *prm, *st, workspace, (hipStream_t)stream));
+}
+
+}  // extern "C"

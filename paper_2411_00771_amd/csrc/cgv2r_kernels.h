@@ -1,0 +1,33 @@
+// Host-side launchers of the gfx950 kernels (one per source file); the C ABI in capi.hip
+// validates arguments and calls these.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/cgv2r.h"
+
+#include "cgv2r_device.h"
+
+hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st);
+hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const uint8_t* flags,
+                                   const float* rg, const cgv2_grads& g, hipStream_t st);
+
+size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, size_t* off);
+hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
+                                void* ws, hipStream_t st);
+
+hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
+                                  int tiles_x, int tiles_y, const cgv2_image& img, hipStream_t st);
+hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
+                                    int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st);
+hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
+                                  int tiles_x, int tiles_y, const cgv2_image& img, const cgv2_image_grad& up,
+                                  float* rg, hipStream_t st);
+
+size_t cgv2_loss_ws_layout(int W, int H, int V, size_t* off);
+hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, int H, float lambda, float* d_img,
+                            float* d_ssim, float* loss, void* ws, hipStream_t st);
+
+size_t cgv2_densify_ws_layout(int64_t n, int V, size_t* off);
+hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const cgv2_grads& g, int V,
+                               const cgv2_densify_params& prm, const cgv2_densify_state& st, void* ws,
+                               hipStream_t stream);

@@ -1,0 +1,386 @@
+// Per-surfel projection (2DGS surfel model of CityGaussianV2 Sec. 3.1, low-pass filter of
+// Sec. 3.2) and its reverse (chain from per-view record gradients to the parameters).
+//
+// One thread per (surfel, view).  Parameters are read as coalesced planar SoA; the geometry
+// (screen transform, centre, inverse homography, conic bound) is computed in FP64, which on
+// MI355X runs at the non-packed FP32 rate and keeps the projected centre exact to ~1e-9 px at
+// 1600-px widths; the kernel is HBM-bound either way.  SH colour is FP32.
+#include "cgv2r_device.h"
+#include "cgv2r_kernels.h"
+
+namespace cgv2 {
+
+// Real spherical harmonics (Condon-Shortley phase, index l*l + l + m) as polynomials in the unit
+// direction; constants are the normalisations sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) times the
+// polynomial factors of the derivatives of P_l.
+struct SH {
+  static constexpr float c0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+  static constexpr float c1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+  static constexpr float c2a = 1.0925484305920792f;   // sqrt(15/(4 pi))
+  static constexpr float c2b = 0.31539156525252005f;  // sqrt(5/(16 pi))
+  static constexpr float c2c = 0.54627421529603959f;  // sqrt(15/(16 pi))
+  static constexpr float c3a = 0.59004358992664352f;  // sqrt(35/(32 pi))
+  static constexpr float c3b = 2.8906114426405538f;   // sqrt(105/(4 pi))
+  static constexpr float c3c = 0.45704579946446572f;  // sqrt(21/(32 pi))
+  static constexpr float c3d = 0.37317633259011540f;  // sqrt(7/(16 pi))
+  static constexpr float c3e = 1.4453057213202769f;   // sqrt(105/(16 pi))
+};
+
+// Y[k] and, if dY != nullptr, the gradient of each polynomial w.r.t. (x, y, z).
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y, float (*dY)[3]) {
+  Y[0] = SH::c0;
+  if (dY) { dY[0][0] = dY[0][1] = dY[0][2] = 0.f; }
+  if (deg < 1) return;
+  Y[1] = -SH::c1 * y; Y[2] = SH::c1 * z; Y[3] = -SH::c1 * x;
+  if (dY) {
+    dY[1][0] = 0.f; dY[1][1] = -SH::c1; dY[1][2] = 0.f;
+    dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = SH::c1;
+    dY[3][0] = -SH::c1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+  }
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = SH::c2a * x * y;
+  Y[5] = -SH::c2a * y * z;
+  Y[6] = SH::c2b * (3.f * zz - 1.f);
+  Y[7] = -SH::c2a * x * z;
+  Y[8] = SH::c2c * (xx - yy);
+  if (dY) {
+    dY[4][0] = SH::c2a * y; dY[4][1] = SH::c2a * x; dY[4][2] = 0.f;
+    dY[5][0] = 0.f; dY[5][1] = -SH::c2a * z; dY[5][2] = -SH::c2a * y;
+    dY[6][0] = 0.f; dY[6][1] = 0.f; dY[6][2] = SH::c2b * 6.f * z;
+    dY[7][0] = -SH::c2a * z; dY[7][1] = 0.f; dY[7][2] = -SH::c2a * x;
+    dY[8][0] = 2.f * SH::c2c * x; dY[8][1] = -2.f * SH::c2c * y; dY[8][2] = 0.f;
+  }
+  if (deg < 3) return;
+  Y[9] = -SH::c3a * y * (3.f * xx - yy);
+  Y[10] = SH::c3b * x * y * z;
+  Y[11] = -SH::c3c * y * (5.f * zz - 1.f);
+  Y[12] = SH::c3d * z * (5.f * zz - 3.f);
+  Y[13] = -SH::c3c * x * (5.f * zz - 1.f);
+  Y[14] = SH::c3e * z * (xx - yy);
+  Y[15] = -SH::c3a * x * (xx - 3.f * yy);
+  if (dY) {
+    dY[9][0] = -SH::c3a * 6.f * x * y; dY[9][1] = -SH::c3a * (3.f * xx - 3.f * yy); dY[9][2] = 0.f;
+    dY[10][0] = SH::c3b * y * z; dY[10][1] = SH::c3b * x * z; dY[10][2] = SH::c3b * x * y;
+    dY[11][0] = 0.f; dY[11][1] = -SH::c3c * (5.f * zz - 1.f); dY[11][2] = -SH::c3c * 10.f * y * z;
+    dY[12][0] = 0.f; dY[12][1] = 0.f; dY[12][2] = SH::c3d * (15.f * zz - 3.f);
+    dY[13][0] = -SH::c3c * (5.f * zz - 1.f); dY[13][1] = 0.f; dY[13][2] = -SH::c3c * 10.f * x * z;
+    dY[14][0] = 2.f * SH::c3e * x * z; dY[14][1] = -2.f * SH::c3e * y * z; dY[14][2] = SH::c3e * (xx - yy);
+    dY[15][0] = -SH::c3a * (3.f * xx - 3.f * yy); dY[15][1] = SH::c3a * 6.f * x * y; dY[15][2] = 0.f;
+  }
+}
+
+struct Geom {
+  double su, sv, o, qn[4], qlen, Rw[9];
+  double pc[3];   // camera-space centre
+  double M[9];    // screen transform, row-major
+  double flip;    // normal orientation (+1 / -1)
+  float nc[3];    // camera-space normal after the flip
+  float dir[3];   // unit view direction (mu - C) / |mu - C|
+  float dist;
+};
+
+__device__ __forceinline__ void rot_from_quat(const double q[4], double R[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+__device__ __forceinline__ void load_geom(const cgv2_surfels& s, const DevCam& c, int64_t i, Geom& g) {
+  const int64_t n = s.n;
+  g.su = (double)expf(s.log_scale[i]);
+  g.sv = (double)expf(s.log_scale[n + i]);
+  g.o = 1.0 / (1.0 + (double)expf(-s.opacity_logit[i]));
+  const double q[4] = {s.quat[i], s.quat[n + i], s.quat[2 * n + i], s.quat[3 * n + i]};
+  g.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double iq = 1.0 / g.qlen;
+  for (int k = 0; k < 4; ++k) g.qn[k] = q[k] * iq;
+  rot_from_quat(g.qn, g.Rw);
+  const double mu[3] = {s.mean[i], s.mean[n + i], s.mean[2 * n + i]};
+  double cu[3], cv[3], ncd[3];
+  for (int r = 0; r < 3; ++r) {
+    const double R0 = c.R[3 * r], R1 = c.R[3 * r + 1], R2 = c.R[3 * r + 2];
+    g.pc[r] = (double)c.t[r] + R0 * mu[0] + R1 * mu[1] + R2 * mu[2];
+    cu[r] = g.su * (R0 * g.Rw[0] + R1 * g.Rw[3] + R2 * g.Rw[6]);
+    cv[r] = g.sv * (R0 * g.Rw[1] + R1 * g.Rw[4] + R2 * g.Rw[7]);
+    ncd[r] = R0 * g.Rw[2] + R1 * g.Rw[5] + R2 * g.Rw[8];
+  }
+  const double* cols[3] = {cu, cv, g.pc};
+  for (int k = 0; k < 3; ++k) {
+    g.M[k] = (double)c.fx * cols[k][0] + (double)c.cx * cols[k][2];
+    g.M[3 + k] = (double)c.fy * cols[k][1] + (double)c.cy * cols[k][2];
+    g.M[6 + k] = cols[k][2];
+  }
+  g.flip = (ncd[0] * g.pc[0] + ncd[1] * g.pc[1] + ncd[2] * g.pc[2]) > 0 ? -1.0 : 1.0;
+  for (int r = 0; r < 3; ++r) g.nc[r] = (float)(g.flip * ncd[r]);
+  // camera centre C = -R^T t
+  double v[3];
+  for (int k = 0; k < 3; ++k) {
+    const double Ck = -((double)c.R[k] * c.t[0] + (double)c.R[3 + k] * c.t[1] + (double)c.R[6 + k] * c.t[2]);
+    v[k] = mu[k] - Ck;
+  }
+  const double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  g.dist = (float)d;
+  for (int k = 0; k < 3; ++k) g.dir[k] = (float)(v[k] / d);
+}
+
+// Centre, inverse-homography coefficients (unscaled) in the centre-shifted pixel frame.
+struct Homog {
+  double cx, cy, al1, al2, be1, be2, A[4], W[3], scale;
+};
+
+__device__ __forceinline__ void homography(const double* M, Homog& h) {
+  h.cx = M[2] / M[8];
+  h.cy = M[5] / M[8];
+  h.al1 = M[0] - h.cx * M[6];
+  h.al2 = M[1] - h.cx * M[7];
+  h.be1 = M[3] - h.cy * M[6];
+  h.be2 = M[4] - h.cy * M[7];
+  const double g1 = M[6], g2 = M[7], g3 = M[8];
+  h.A[0] = g3 * h.be2;
+  h.A[1] = -g3 * h.al2;
+  h.A[2] = -g3 * h.be1;
+  h.A[3] = g3 * h.al1;
+  h.W[0] = h.al1 * h.be2 - h.al2 * h.be1;
+  h.W[1] = h.be1 * g2 - h.be2 * g1;
+  h.W[2] = g1 * h.al2 - g2 * h.al1;
+  double m = 0;
+  for (int k = 0; k < 4; ++k) m = fmax(m, fabs(h.A[k]));
+  for (int k = 0; k < 3; ++k) m = fmax(m, fabs(h.W[k]));
+  h.scale = m > 0 ? 1.0 / m : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, cgv2_proj out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = cams.v0 + (int)blockIdx.y;
+  const int64_t n = s.n;
+  if (i >= n) return;
+  const DevCam& c = cams.c[blockIdx.y];
+  const int64_t vi = (int64_t)v * n + i;
+  uint16_t* rect = out.rect + 4 * vi;
+  Geom g;
+  load_geom(s, c, i, g);
+  unsigned fl = 0;
+  bool finite = isfinite(g.o) && isfinite(g.su) && isfinite(g.sv) && isfinite(g.qlen) && g.qlen > 0;
+  for (int k = 0; k < 9; ++k) finite = finite && isfinite(g.M[k]);
+  const double k2 = 2.0 * log(255.0 * g.o);
+  if (!finite) fl = CGV2_F_NONFINITE;
+  else if (!(g.M[8] > (double)c.znear)) fl = CGV2_F_NEAR;
+  else if (!(k2 > 0)) fl = CGV2_F_OPACITY;
+  double Q33 = 0;
+  if (!fl) {
+    Q33 = g.M[6] * g.M[6] + g.M[7] * g.M[7] - g.M[8] * g.M[8] / k2;
+    if (!(Q33 < 0)) fl = CGV2_F_BEHIND;
+  }
+  if (fl) {
+    out.flags[vi] = (uint8_t)fl;
+    out.radius[vi] = 0.f;
+    *(uint2*)rect = make_uint2(0u, 0u);
+    return;
+  }
+  const double* M = g.M;
+  const double ik2 = 1.0 / k2;
+  const double Q13 = M[0] * M[6] + M[1] * M[7] - M[2] * M[8] * ik2;
+  const double Q23 = M[3] * M[6] + M[4] * M[7] - M[5] * M[8] * ik2;
+  const double Q11 = M[0] * M[0] + M[1] * M[1] - M[2] * M[2] * ik2;
+  const double Q22 = M[3] * M[3] + M[4] * M[4] - M[5] * M[5] * ik2;
+  const double xb = Q13 / Q33, yb = Q23 / Q33;
+  const double ex = sqrt(fmax(0.0, xb * xb - Q11 / Q33));
+  const double ey = sqrt(fmax(0.0, yb * yb - Q22 / Q33));
+  Homog h;
+  homography(M, h);
+  const double rf = sqrt(0.5 * k2);
+  // a 1e-4 px pad keeps every pixel the exact bound includes, whatever the rounding
+  const double pad = 1e-4;
+  const double xlo = fmin(xb - ex, h.cx - rf) - pad, xhi = fmax(xb + ex, h.cx + rf) + pad;
+  const double ylo = fmin(yb - ey, h.cy - rf) - pad, yhi = fmax(yb + ey, h.cy + rf) + pad;
+  // low-pass dominance at the sample nearest the centre
+  {
+    const double xr = floor(h.cx) + 0.5 - h.cx, yr = floor(h.cy) + 0.5 - h.cy;
+    const double P1 = h.A[0] * xr + h.A[1] * yr, P2 = h.A[2] * xr + h.A[3] * yr;
+    const double w = h.W[0] + h.W[1] * xr + h.W[2] * yr;
+    const double rho2 = 2.0 * (xr * xr + yr * yr);
+    // rho2 < rho3 = (P1^2 + P2^2) / w^2
+    if (rho2 * w * w < P1 * P1 + P2 * P2) fl |= CGV2_F_LOWPASS;
+  }
+  const double i0 = fmax(0.0, ceil(xlo - 0.5)), i1 = fmin((double)(c.W - 1), floor(xhi - 0.5));
+  const double j0 = fmax(0.0, ceil(ylo - 0.5)), j1 = fmin((double)(c.H - 1), floor(yhi - 0.5));
+  out.radius[vi] = (float)fmax(fmax(ex, ey), rf);
+  if (!(i0 <= i1 && j0 <= j1)) {
+    out.flags[vi] = (uint8_t)fl;
+    *(uint2*)rect = make_uint2(0u, 0u);
+    return;
+  }
+  fl |= CGV2_F_VISIBLE;
+  out.flags[vi] = (uint8_t)fl;
+  const uint32_t tx0 = (uint32_t)i0 / kTile, tx1 = (uint32_t)i1 / kTile + 1;
+  const uint32_t ty0 = (uint32_t)j0 / kTile, ty1 = (uint32_t)j1 / kTile + 1;
+  *(uint2*)rect = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
+
+  // SH colour
+  const int K = (s.sh_degree + 1) * (s.sh_degree + 1);
+  float Y[16];
+  sh_basis(s.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
+  float col[3];
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = 0.5f;
+    for (int k = 0; k < K; ++k) acc = fmaf(s.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], acc);
+    col[ch] = fmaxf(acc, 0.f);
+  }
+  // record
+  const double cxh = rint(fmin(fmax(h.cx, -16777216.0), 16777216.0));
+  const double cyh = rint(fmin(fmax(h.cy, -16777216.0), 16777216.0));
+  float4* rp = (float4*)(out.rec + (size_t)vi * kRec);
+  const double sc = h.scale;
+  rp[0] = make_float4((float)cxh, (float)cyh, (float)(h.cx - cxh), (float)(h.cy - cyh));
+  rp[1] = make_float4((float)(h.A[0] * sc), (float)(h.A[1] * sc), (float)(h.A[2] * sc), (float)(h.A[3] * sc));
+  rp[2] = make_float4((float)(h.W[0] * sc), (float)(h.W[1] * sc), (float)(h.W[2] * sc), (float)M[8]);
+  rp[3] = make_float4((float)g.o, col[0], col[1], col[2]);
+  rp[4] = make_float4(g.nc[0], g.nc[1], g.nc[2], (float)k2);
+}
+
+// ------------------------------------------------------------------------------------------
+// Reverse: record gradients of every view -> parameter gradients (+=), view-space gradients.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cams,
+                                                      const uint8_t* __restrict__ flags,
+                                                      const float* __restrict__ rg, cgv2_grads gr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = s.n;
+  if (i >= n) return;
+  const int K = (s.sh_degree + 1) * (s.sh_degree + 1);
+  double dmu[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dls[2] = {0, 0}, dlogit = 0;
+  float dsh[48];
+  for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
+  bool any = false;
+  for (int lv = 0; lv < cams.count; ++lv) {
+    const int v = cams.v0 + lv;
+    const int64_t vi = (int64_t)v * n + i;
+    const DevCam& c = cams.c[lv];
+    float* gvt = gr.g_view_total ? gr.g_view_total + (int64_t)v * 2 * n : nullptr;
+    float* gvs = gr.g_view_ssim ? gr.g_view_ssim + (int64_t)v * 2 * n : nullptr;
+    if (!(flags[vi] & CGV2_F_VISIBLE)) {
+      if (gvt) { gvt[i] = 0.f; gvt[n + i] = 0.f; }
+      if (gvs) { gvs[i] = 0.f; gvs[n + i] = 0.f; }
+      continue;
+    }
+    any = true;
+    const float* r = rg + (int64_t)v * kGradFields * n + i;
+    float d[kGradFields];
+    for (int k = 0; k < kGradFields; ++k) d[k] = r[(int64_t)k * n];
+    const float ndx = 0.5f * (float)c.W, ndy = 0.5f * (float)c.H;
+    if (gvt) { gvt[i] = d[G_CX] * ndx; gvt[n + i] = d[G_CY] * ndy; }
+    if (gvs) { gvs[i] = d[G_SCX] * ndx; gvs[n + i] = d[G_SCY] * ndy; }
+
+    Geom g;
+    load_geom(s, c, i, g);
+    Homog h;
+    homography(g.M, h);
+    const double* M = g.M;
+    // record -> (alpha, beta, gamma) -> M; the common scale of the coefficients leaves every
+    // output unchanged, so it is held constant
+    const double sc = h.scale;
+    const double dA11 = d[G_A11] * sc, dA12 = d[G_A12] * sc, dA21 = d[G_A21] * sc, dA22 = d[G_A22] * sc;
+    const double dW0 = d[G_W0] * sc, dW1 = d[G_W1] * sc, dW2 = d[G_W2] * sc;
+    const double g1 = M[6], g2 = M[7], g3 = M[8];
+    const double dal1 = dA22 * g3 + dW0 * h.be2 - dW2 * g2;
+    const double dal2 = -dA12 * g3 - dW0 * h.be1 + dW2 * g1;
+    const double dbe1 = -dA21 * g3 - dW0 * h.al2 + dW1 * g2;
+    const double dbe2 = dA11 * g3 + dW0 * h.al1 - dW1 * g1;
+    const double dg1 = -dW1 * h.be2 + dW2 * h.al2;
+    const double dg2 = dW1 * h.be1 - dW2 * h.al1;
+    const double dg3 = dA11 * h.be2 - dA12 * h.al2 - dA21 * h.be1 + dA22 * h.al1 + d[G_ZC];
+    double dM[9];
+    dM[0] = dal1; dM[1] = dal2; dM[3] = dbe1; dM[4] = dbe2;
+    dM[6] = dg1 - dal1 * h.cx - dbe1 * h.cy;
+    dM[7] = dg2 - dal2 * h.cx - dbe2 * h.cy;
+    const double dcx = (double)d[G_CX] - dal1 * M[6] - dal2 * M[7];
+    const double dcy = (double)d[G_CY] - dbe1 * M[6] - dbe2 * M[7];
+    dM[2] = dcx / M[8];
+    dM[5] = dcy / M[8];
+    dM[8] = dg3 - (dcx * h.cx + dcy * h.cy) / M[8];
+    // M columns = K_int [cu | cv | pc]
+    double vw[3][3];
+    for (int k = 0; k < 3; ++k) {
+      const double a = (double)c.fx * dM[k], b = (double)c.fy * dM[3 + k];
+      const double e = (double)c.cx * dM[k] + (double)c.cy * dM[3 + k] + dM[6 + k];
+      for (int r2 = 0; r2 < 3; ++r2) vw[k][r2] = (double)c.R[r2] * a + (double)c.R[3 + r2] * b + (double)c.R[6 + r2] * e;
+    }
+    double dsu = 0, dsv = 0, dR[9];
+    for (int r2 = 0; r2 < 3; ++r2) {
+      dsu += vw[0][r2] * g.Rw[3 * r2];
+      dsv += vw[1][r2] * g.Rw[3 * r2 + 1];
+      dR[3 * r2] = g.su * vw[0][r2];
+      dR[3 * r2 + 1] = g.sv * vw[1][r2];
+      dmu[r2] += vw[2][r2];
+    }
+    const double dn[3] = {d[G_NX], d[G_NY], d[G_NZ]};
+    for (int r2 = 0; r2 < 3; ++r2)
+      dR[3 * r2 + 2] = g.flip * ((double)c.R[r2] * dn[0] + (double)c.R[3 + r2] * dn[1] + (double)c.R[6 + r2] * dn[2]);
+    // rotation -> normalised quaternion
+    {
+      const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+      double dqn[4];
+      dqn[0] = -2 * z * dR[1] + 2 * y * dR[2] + 2 * z * dR[3] - 2 * x * dR[5] - 2 * y * dR[6] + 2 * x * dR[7];
+      dqn[1] = 2 * y * dR[1] + 2 * z * dR[2] + 2 * y * dR[3] - 4 * x * dR[4] - 2 * w * dR[5] + 2 * z * dR[6] +
+               2 * w * dR[7] - 4 * x * dR[8];
+      dqn[2] = -4 * y * dR[0] + 2 * x * dR[1] + 2 * w * dR[2] + 2 * x * dR[3] + 2 * z * dR[5] - 2 * w * dR[6] +
+               2 * z * dR[7] - 4 * y * dR[8];
+      dqn[3] = -4 * z * dR[0] - 2 * w * dR[1] + 2 * x * dR[2] + 2 * w * dR[3] - 4 * z * dR[4] + 2 * y * dR[5] +
+               2 * x * dR[6] + 2 * y * dR[7];
+      const double dot = g.qn[0] * dqn[0] + g.qn[1] * dqn[1] + g.qn[2] * dqn[2] + g.qn[3] * dqn[3];
+      for (int k = 0; k < 4; ++k) dq[k] += (dqn[k] - g.qn[k] * dot) / g.qlen;
+    }
+    dls[0] += dsu * g.su;
+    dls[1] += dsv * g.sv;
+    dlogit += (double)d[G_OP] * g.o * (1 - g.o);
+    // colour through SH
+    float Y[16], dY[16][3];
+    sh_basis(s.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y, dY);
+    float ddir[3] = {0.f, 0.f, 0.f};
+    const float dcol[3] = {d[G_R], d[G_G], d[G_B]};
+    for (int ch = 0; ch < 3; ++ch) {
+      float raw = 0.5f;
+      float f[16];
+      for (int k = 0; k < K; ++k) {
+        f[k] = s.sh[(int64_t)(k * 3 + ch) * n + i];
+        raw = fmaf(f[k], Y[k], raw);
+      }
+      if (raw < 0.f) continue;
+      for (int k = 0; k < K; ++k) {
+        dsh[k * 3 + ch] = fmaf(dcol[ch], Y[k], dsh[k * 3 + ch]);
+        const float gf = dcol[ch] * f[k];
+        ddir[0] = fmaf(gf, dY[k][0], ddir[0]);
+        ddir[1] = fmaf(gf, dY[k][1], ddir[1]);
+        ddir[2] = fmaf(gf, dY[k][2], ddir[2]);
+      }
+    }
+    const float dd = ddir[0] * g.dir[0] + ddir[1] * g.dir[1] + ddir[2] * g.dir[2];
+    for (int k = 0; k < 3; ++k) dmu[k] += (double)((ddir[k] - g.dir[k] * dd) / g.dist);
+  }
+  if (!any) return;
+  for (int k = 0; k < 3; ++k) gr.d_mean[k * n + i] += (float)dmu[k];
+  for (int k = 0; k < 4; ++k) gr.d_quat[k * n + i] += (float)dq[k];
+  gr.d_log_scale[i] += (float)dls[0];
+  gr.d_log_scale[n + i] += (float)dls[1];
+  gr.d_opacity_logit[i] += (float)dlogit;
+  for (int k = 0; k < 3 * K; ++k) gr.d_sh[(int64_t)k * n + i] += dsh[k];
+}
+
+}  // namespace cgv2
+
+hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)cams.count);
+  hipLaunchKernelGGL(cgv2::k_project, grid, dim3(256), 0, st, s, cams, p);
+  return hipGetLastError();
+}
+
+hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const uint8_t* flags,
+                                   const float* rg, const cgv2_grads& g, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cgv2::k_project_bwd, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s, cams, flags, rg,
+                     g);
+  return hipGetLastError();
+}

@@ -1,0 +1,281 @@
+"""Device-resident rasterizer engine over the C ABI, and its torch.autograd form.
+
+PyTorch supplies device memory and the stream; every step runs in libcgv2r's kernels.
+
+    eng = Engine(n, width, height, views=1, capacity=...)
+    eng.project(params, cams); eng.bin_sort(cams); eng.render(cams)
+    eng.loss(target); eng.backward(params, cams, grads); eng.densify(params, cams, state)
+
+``Rasterize2DGS`` / ``L1SSIMLoss`` wrap the same calls as autograd Functions: the loss's backward
+stores the SSIM-only image gradient on the engine, and the rasterizer's backward consumes it to
+produce the decomposed densification gradient (CityGaussianV2 Eq. 2) next to the total one.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, ptr
+
+LAMBDA_SSIM = 0.2
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Params:
+    """Surfel parameters on the device (planar SoA float32), from a generators' Scene or tensors."""
+
+    def __init__(self, mean, log_scale, quat, opacity_logit, sh, sh_degree: int):
+        self.mean, self.log_scale, self.quat = mean, log_scale, quat
+        self.opacity_logit, self.sh, self.sh_degree = opacity_logit, sh, sh_degree
+        for t in (mean, log_scale, quat, opacity_logit, sh):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        f = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float32).contiguous()
+        return cls(f(scene.mean), f(scene.log_scale), f(scene.quat), f(scene.opacity_logit), f(scene.sh),
+                   scene.sh_degree)
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+    def struct(self) -> _lib.Surfels:
+        s = _lib.Surfels()
+        s.n, s.sh_degree = self.n, self.sh_degree
+        s.mean, s.log_scale, s.quat = ptr(self.mean), ptr(self.log_scale), ptr(self.quat)
+        s.opacity_logit, s.sh = ptr(self.opacity_logit), ptr(self.sh)
+        return s
+
+    def zeros_like(self) -> "Params":
+        return Params(*(torch.zeros_like(t) for t in (self.mean, self.log_scale, self.quat, self.opacity_logit,
+                                                       self.sh)), self.sh_degree)
+
+
+class Grads:
+    """Parameter gradients (+=) and the per-view total / SSIM-only view-space gradients."""
+
+    def __init__(self, params: Params, views: int):
+        z = params.zeros_like()
+        self.mean, self.log_scale, self.quat, self.opacity_logit, self.sh = (z.mean, z.log_scale, z.quat,
+                                                                           z.opacity_logit, z.sh)
+        n = params.n
+        dev = params.mean.device
+        self.g_view_total = torch.zeros((views, 2, n), device=dev)
+        self.g_view_ssim = torch.zeros((views, 2, n), device=dev)
+
+    def zero_(self):
+        for t in (self.mean, self.log_scale, self.quat, self.opacity_logit, self.sh):
+            t.zero_()
+
+    def struct(self) -> _lib.Grads:
+        g = _lib.Grads()
+        g.d_mean, g.d_log_scale, g.d_quat = ptr(self.mean), ptr(self.log_scale), ptr(self.quat)
+        g.d_opacity_logit, g.d_sh = ptr(self.opacity_logit), ptr(self.sh)
+        g.g_view_total, g.g_view_ssim = ptr(self.g_view_total), ptr(self.g_view_ssim)
+        return g
+
+
+class DensifyState:
+    def __init__(self, n: int, views: int = 1, device="cuda"):
+        self.accum_dgd = torch.zeros(n, device=device)
+        self.accum_total = torch.zeros(n, device=device)
+        self.max_radius = torch.zeros(n, device=device)
+        self.denom = torch.zeros(n, dtype=torch.int32, device=device)
+        self.mask = torch.zeros(n, dtype=torch.uint8, device=device)
+        self.counters = torch.zeros(8, dtype=torch.int32, device=device)
+        self.scale = torch.zeros(max(views, 1), device=device)
+
+    def reset(self):
+        for t in (self.accum_dgd, self.accum_total, self.max_radius, self.denom, self.mask, self.counters):
+            t.zero_()
+
+    def struct(self) -> _lib.DensifyState:
+        s = _lib.DensifyState()
+        s.accum_dgd, s.accum_total, s.max_radius = ptr(self.accum_dgd), ptr(self.accum_total), ptr(self.max_radius)
+        s.denom, s.mask, s.counters, s.scale = ptr(self.denom), ptr(self.mask), ptr(self.counters), ptr(self.scale)
+        return s
+
+
+class Engine:
+    """Buffers for V views of one resolution and n surfels; each method is one C-ABI call."""
+
+    def __init__(self, n: int, width: int, height: int, views: int = 1, capacity: Optional[int] = None,
+                 device="cuda", backward: bool = True):
+        L = _lib.lib()
+        self.n, self.W, self.H, self.V = int(n), int(width), int(height), int(views)
+        self.tiles_x = (self.W + 15) // 16
+        self.tiles_y = (self.H + 15) // 16
+        self.tiles = self.tiles_x * self.tiles_y
+        self.device = device
+        V, H, W = self.V, self.H, self.W
+        vn = max(V * n, 1)
+        self.rec = torch.empty(vn * _lib.REC_FLOATS, device=device)
+        self.rect = torch.empty(vn * 4, dtype=torch.int16, device=device)
+        self.radius = torch.empty(vn, device=device)
+        self.flags = torch.empty(vn, dtype=torch.uint8, device=device)
+        self.ranges = torch.zeros(V * self.tiles + 1, dtype=torch.int32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.needed = torch.zeros(1, dtype=torch.int64, device=device)
+        self.rgb = torch.empty((V, 3, H, W), device=device)
+        self.depth = torch.empty((V, H, W), device=device)
+        self.depth_med = torch.empty((V, H, W), device=device)
+        self.normal = torch.empty((V, 3, H, W), device=device)
+        self.alpha = torch.empty((V, H, W), device=device)
+        self.T_final = torch.empty((V, H, W), device=device)
+        self.last = torch.empty((V, H, W), dtype=torch.int32, device=device)
+        self.med = torch.empty((V, H, W), dtype=torch.int32, device=device)
+        self.backward_enabled = backward
+        if backward:
+            self.d_img = torch.empty((V, 3, H, W), device=device)
+            self.d_img_ssim = torch.empty((V, 3, H, W), device=device)
+            self.loss_val = torch.zeros((V, 3), device=device)
+            self.ws_loss = torch.empty(L.cgv2_loss_workspace(W, H, V), dtype=torch.uint8, device=device)
+            self.ws_bwd = torch.empty(max(L.cgv2_render_bwd_workspace(n, V), 256), dtype=torch.uint8, device=device)
+            self.ws_dens = torch.empty(max(L.cgv2_densify_workspace(n, V), 256), dtype=torch.uint8, device=device)
+        self.pending_ssim = None
+        self.set_capacity(capacity if capacity is not None else max(1 << 20, 16 * n * V))
+        self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags))
+        self._img = _lib.Image(ptr(self.rgb), ptr(self.depth), ptr(self.depth_med), ptr(self.normal),
+                               ptr(self.alpha), ptr(self.T_final), ptr(self.last), ptr(self.med))
+
+    def set_capacity(self, capacity: int):
+        L = _lib.lib()
+        self.capacity = int(capacity)
+        self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+        self.ws_bin = torch.empty(L.cgv2_bin_sort_workspace(self.capacity, self.V, self.tiles), dtype=torch.uint8,
+                                  device=self.device)
+        self._bins = _lib.Bins(self.capacity, ptr(self.ids), ptr(self.ranges), ptr(self.status), ptr(self.needed))
+
+    # ---- the five calls (+ loss) -------------------------------------------------------------
+    def cams(self, cams: Sequence) -> ctypes.Array:
+        assert len(cams) == self.V
+        for c in cams:
+            assert c.width == self.W and c.height == self.H
+        return _lib.camera_array(cams)
+
+    def project(self, params: Params, cams):
+        check(_lib.lib().cgv2_project(ctypes.byref(params.struct()), cams, self.V, ctypes.byref(self._proj),
+                                      _stream()), "cgv2_project")
+
+    def bin_sort(self, cams):
+        check(_lib.lib().cgv2_bin_sort(ctypes.byref(self._proj), cams, self.V, self.n, ctypes.byref(self._bins),
+                                       ptr(self.ws_bin), self.ws_bin.numel(), _stream()), "cgv2_bin_sort")
+
+    def render(self, cams):
+        check(_lib.lib().cgv2_render_fwd(ctypes.byref(self._proj), ctypes.byref(self._bins), cams, self.V, self.n,
+                                         ctypes.byref(self._img), _stream()), "cgv2_render_fwd")
+
+    def count(self, cams):
+        """(evaluated, contributing, reverse-walked) pixel-entry pairs of the current bins."""
+        c = torch.zeros(3, dtype=torch.int64, device=self.device)
+        check(_lib.lib().cgv2_render_count(ctypes.byref(self._proj), ctypes.byref(self._bins), cams, self.V, self.n,
+                                           ptr(c), _stream()), "cgv2_render_count")
+        return [int(x) for x in c.cpu()]
+
+    def loss(self, target, lam: float = LAMBDA_SSIM, img=None):
+        img = self.rgb if img is None else img
+        check(_lib.lib().cgv2_loss(ptr(img), ptr(target), self.V, self.W, self.H, lam, ptr(self.d_img),
+                                   ptr(self.d_img_ssim), ptr(self.loss_val), ptr(self.ws_loss), self.ws_loss.numel(),
+                                   _stream()), "cgv2_loss")
+        return self.loss_val
+
+    def backward(self, params: Params, cams, grads: Grads, d_rgb=None, d_depth=None, d_depth_med=None,
+                 d_normal=None, d_alpha=None, d_rgb_ssim=None):
+        up = _lib.ImageGrad(ptr(d_rgb), ptr(d_depth), ptr(d_depth_med), ptr(d_normal), ptr(d_alpha),
+                            ptr(d_rgb_ssim))
+        check(_lib.lib().cgv2_render_bwd(ctypes.byref(params.struct()), ctypes.byref(self._proj),
+                                         ctypes.byref(self._bins), cams, self.V, ctypes.byref(self._img),
+                                         ctypes.byref(up), ctypes.byref(grads.struct()), ptr(self.ws_bwd),
+                                         self.ws_bwd.numel(), _stream()), "cgv2_render_bwd")
+
+    def densify(self, params: Params, grads: Grads, state: DensifyState, omega=0.9, eta_min=0.05,
+                grad_threshold=2e-4):
+        prm = _lib.DensifyParams(omega, eta_min, grad_threshold)
+        check(_lib.lib().cgv2_densify_stats(ctypes.byref(params.struct()), ctypes.byref(self._proj),
+                                            ctypes.byref(grads.struct()), self.V, ctypes.byref(prm),
+                                            ctypes.byref(state.struct()), ptr(self.ws_dens), self.ws_dens.numel(),
+                                            _stream()), "cgv2_densify_stats")
+
+    # ---- helpers -------------------------------------------------------------------------------
+    def overflowed(self) -> bool:
+        return bool(self.status.item() != 0)
+
+    def fit_capacity(self, params: Params, cams, slack: float = 1.25):
+        """Project + bin once, read the intersection count and size the bins (synchronises)."""
+        self.project(params, cams)
+        self.status.zero_()
+        self.bin_sort(cams)
+        need = int(self.needed.item())
+        if need > self.capacity or self.status.item() != 0:
+            self.set_capacity(int(need * slack) + 1024)
+            self.status.zero_()
+        return need
+
+    def forward(self, params: Params, cams):
+        self.project(params, cams)
+        self.bin_sort(cams)
+        self.render(cams)
+
+
+# ------------------------------------------------------------------------------------------------
+# autograd form
+# ------------------------------------------------------------------------------------------------
+
+class Rasterize2DGS(torch.autograd.Function):
+    """(mean, log_scale, quat, opacity_logit, sh) -> (rgb, depth, depth_med, normal, alpha) of V views.
+
+    Saves nothing per fragment: the backward reads the engine's bins and the per-pixel
+    checkpoint (T_final, last, med) written by the forward.  Gradients go to the parameters;
+    the engine's ``grads`` also receives the total and SSIM-only view-space gradients.
+    """
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, sh, engine: Engine, cams, sh_degree: int):
+        params = Params(mean.detach(), log_scale.detach(), quat.detach(), opacity_logit.detach(), sh.detach(),
+                        sh_degree)
+        engine.forward(params, cams)
+        ctx.engine, ctx.cams, ctx.params = engine, cams, params
+        return engine.rgb, engine.depth, engine.depth_med, engine.normal, engine.alpha
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_depth, d_depth_med, d_normal, d_alpha):
+        eng: Engine = ctx.engine
+        p = ctx.params
+        if getattr(eng, "grads", None) is None or eng.grads.mean.shape != p.mean.shape:
+            eng.grads = Grads(p, eng.V)
+        g = eng.grads
+        g.zero_()
+        c = lambda t: None if t is None else t.contiguous()
+        eng.backward(p, ctx.cams, g, d_rgb=c(d_rgb), d_depth=c(d_depth), d_depth_med=c(d_depth_med),
+                     d_normal=c(d_normal), d_alpha=c(d_alpha), d_rgb_ssim=eng.pending_ssim)
+        eng.pending_ssim = None
+        return g.mean.clone(), g.log_scale.clone(), g.quat.clone(), g.opacity_logit.clone(), g.sh.clone(), None, \
+            None, None
+
+
+class L1SSIMLoss(torch.autograd.Function):
+    """Per-view (1 - lambda) L1 + lambda (1 - SSIM), summed over views; its backward hands the
+    SSIM-only image gradient to the engine for the decomposed densification gradient."""
+
+    @staticmethod
+    def forward(ctx, rgb, target, engine: Engine, lam: float):
+        lv = engine.loss(target.contiguous(), lam, img=rgb.contiguous())
+        ctx.engine = engine
+        return lv[:, 0].sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        eng: Engine = ctx.engine
+        eng.pending_ssim = eng.d_img_ssim * g if not isinstance(g, float) else eng.d_img_ssim
+        return eng.d_img * g, None, None, None
+
+
+def rasterize(params_t, engine: Engine, cams, sh_degree: int):
+    return Rasterize2DGS.apply(*params_t, engine, cams, sh_degree)

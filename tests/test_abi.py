@@ -1,0 +1,114 @@
+"""The C-ABI library: loads, exports every entry point of include/cgv2r.h, validates arguments and
+sizes workspaces without touching a GPU (every case here returns before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2411_00771_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgv2r.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgv2_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_header_constants_match_binding():
+    txt = open(HEADER).read()
+    assert re.search(r"#define CGV2_REC_FLOATS (\d+)", txt).group(1) == str(_lib.REC_FLOATS)
+    assert re.search(r"#define CGV2_TILE (\d+)", txt).group(1) == str(_lib.TILE)
+    assert ctypes.sizeof(_lib.Camera) == 4 * (2 + 4 + 9 + 3 + 1 + 3)
+
+
+def test_strerror_and_workspace_sizes():
+    L = _lib.lib()
+    assert L.cgv2_strerror(0) == b"ok" and L.cgv2_strerror(-2) == b"workspace too small"
+    a = L.cgv2_bin_sort_workspace(1 << 20, 1, 6700)
+    b = L.cgv2_bin_sort_workspace(1 << 21, 1, 6700)
+    assert b - a >= 16 * (1 << 20)  # two u64 arrays per intersection
+    assert L.cgv2_bin_sort_workspace(-1, 1, 10) == 0 and L.cgv2_bin_sort_workspace(10, 0, 10) == 0
+    assert L.cgv2_render_bwd_workspace(1000, 2) >= 19 * 4 * 1000 * 2
+    assert L.cgv2_loss_workspace(0, 10, 1) == 0
+    assert L.cgv2_densify_workspace(10, 1) > 0
+
+
+def _fake_proj():
+    return _lib.Proj(ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), ctypes.c_void_p(1024))
+
+
+def test_argument_validation_returns_einval():
+    L = _lib.lib()
+    cam = _lib.Camera()
+    cam.width, cam.height = 64, 64
+    cams = (_lib.Camera * 2)(cam, cam)
+    s = _lib.Surfels(10, 3, *[ctypes.c_void_p(256)] * 5)
+    p = _fake_proj()
+    EINVAL = _lib.CGV2_EINVAL
+    assert L.cgv2_project(None, cams, 1, ctypes.byref(p), None) == EINVAL
+    assert L.cgv2_project(ctypes.byref(s), cams, 0, ctypes.byref(p), None) == EINVAL
+    bad = _lib.Surfels(10, 4, *[ctypes.c_void_p(256)] * 5)
+    assert L.cgv2_project(ctypes.byref(bad), cams, 1, ctypes.byref(p), None) == EINVAL
+    neg = _lib.Surfels(-1, 3, *[ctypes.c_void_p(256)] * 5)
+    assert L.cgv2_project(ctypes.byref(neg), cams, 1, ctypes.byref(p), None) == EINVAL
+    nul = _lib.Surfels(10, 3, None, None, None, None, None)
+    assert L.cgv2_project(ctypes.byref(nul), cams, 1, ctypes.byref(p), None) == EINVAL
+    other = _lib.Camera()
+    other.width, other.height = 32, 64
+    mixed = (_lib.Camera * 2)(cam, other)
+    assert L.cgv2_project(ctypes.byref(s), mixed, 2, ctypes.byref(p), None) == EINVAL
+    zero = _lib.Camera()
+    assert L.cgv2_project(ctypes.byref(s), ctypes.byref(zero), 1, ctypes.byref(p), None) == EINVAL
+    huge = _lib.Camera()
+    huge.width, huge.height = 16 * 70000, 16
+    assert L.cgv2_project(ctypes.byref(s), ctypes.byref(huge), 1, ctypes.byref(p), None) == EINVAL
+    bins = _lib.Bins(100, ctypes.c_void_p(256), None, ctypes.c_void_p(256), ctypes.c_void_p(256))
+    assert L.cgv2_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(bins), ctypes.c_void_p(256), 1 << 30,
+                           None) == EINVAL
+    img = _lib.Image()
+    assert L.cgv2_render_fwd(ctypes.byref(p), None, cams, 1, 10, ctypes.byref(img), None) == EINVAL
+    assert L.cgv2_loss(None, None, 1, 8, 8, 0.2, None, None, None, None, 0, None) == EINVAL
+    g = _lib.Grads()
+    up = _lib.ImageGrad()
+    okbins = _lib.Bins(100, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256))
+    # backward without the forward checkpoint
+    assert L.cgv2_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(okbins), cams, 1, ctypes.byref(img),
+                             ctypes.byref(up), ctypes.byref(g), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
+    prm = _lib.DensifyParams(0.9, 0.05, 2e-4)
+    st = _lib.DensifyState()
+    assert L.cgv2_densify_stats(ctypes.byref(s), ctypes.byref(p), ctypes.byref(g), 1, ctypes.byref(prm),
+                                ctypes.byref(st), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
+
+
+def test_small_workspace_returns_eworkspace():
+    L = _lib.lib()
+    cam = _lib.Camera()
+    cam.width, cam.height = 64, 64
+    p = _fake_proj()
+    bins = _lib.Bins(1000, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256))
+    need = L.cgv2_bin_sort_workspace(1000, 1, 16)
+    assert L.cgv2_bin_sort(ctypes.byref(p), ctypes.byref(cam), 1, 10, ctypes.byref(bins), ctypes.c_void_p(256),
+                           need - 1, None) == _lib.CGV2_EWORKSPACE
+    v = ctypes.c_void_p(256)
+    assert L.cgv2_loss(v, v, 1, 64, 64, 0.2, v, v, v, v, L.cgv2_loss_workspace(64, 64, 1) - 1,
+                       None) == _lib.CGV2_EWORKSPACE
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(_lib.Cgv2Error):
+        _lib.lib()

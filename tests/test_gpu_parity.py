@@ -1,0 +1,296 @@
+"""HIP path vs the FP64 oracle on the tiny workload (4,096 surfels, 128x128) and edge cases.
+
+Every call goes through the C ABI (libcgv2r.so).  Tolerances: images 1e-4 max abs on pixels whose
+decision margins are not fragile; per-tile lists bit-exact; gradients 1e-3 relative per group.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_00771_amd import scenes
+from tests.helpers import (FRAGILE, compare_images, fetch_bins, fetch_img, fetch_proj, gpu_forward, grad_close)
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_all(sc, cam):
+    return oracle.forward_view(sc, cam)
+
+
+@pytest.fixture(scope="module")
+def tiny(cuda):
+    w = scenes.workload(0)
+    sc, cam, tgt = w["scene"], w["cameras"][0], w["targets"][0]
+    eng, params, cs = gpu_forward(sc, [cam], capacity=1 << 16)
+    po, off, ids, io = _oracle_all(sc, cam)
+    return dict(sc=sc, cam=cam, tgt=tgt, eng=eng, params=params, cs=cs, po=po, off=off, ids=ids, io=io)
+
+
+def test_project_matches_oracle(tiny):
+    P = fetch_proj(tiny["eng"])
+    po = tiny["po"]
+    rec, fl = P["rec"][0], P["flags"][0]
+    cull = 2 | 4 | 8 | 16
+    assert np.array_equal(fl & cull, po["flags"] & cull)
+    vis_o = (po["flags"] & 1) > 0
+    vis = (fl & 1) > 0
+    assert np.array_equal(vis, vis_o)
+    v = vis
+    assert np.abs(rec[v, 13:16] - po["rgb"][v]).max() <= 2e-6
+    assert np.abs(rec[v, 16:19] - po["normal"][v]).max() <= 1e-6
+    assert np.abs(rec[v, 12] - po["opacity"][v]).max() <= 1e-6
+    assert np.abs(rec[v, 11] / po["depth"][v] - 1).max() <= 1e-6
+    M = po["M"][v]
+    cx = rec[v, 0].astype(np.float64) + rec[v, 2]
+    cy = rec[v, 1].astype(np.float64) + rec[v, 3]
+    assert np.abs(cx - M[:, 2] / M[:, 8]).max() <= 1e-5
+    assert np.abs(cy - M[:, 5] / M[:, 8]).max() <= 1e-5
+    assert np.array_equal(P["rect"][0][v], po["tile_rect"][v])
+    assert np.abs(P["radius"][0][v] / po["radius"][v] - 1).max() <= 1e-5
+    # inverse homography: rho_3d and the intersection depth at offsets from the centre
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        d = rng.normal(size=2) * 2.0
+        xr, yr = d
+        a11, a12, a21, a22, w0, w1, w2 = [rec[v, k].astype(np.float64) for k in range(4, 11)]
+        P1, P2, w = a11 * xr + a12 * yr, a21 * xr + a22 * yr, w0 + w1 * xr + w2 * yr
+        rho = (P1 ** 2 + P2 ** 2) / w ** 2
+        zf = rec[v, 11] * w0 / w
+        x, y = M[:, 2] / M[:, 8] + xr, M[:, 5] / M[:, 8] + yr
+        a = x[:, None] * M[:, 6:9] - M[:, 0:3]
+        b = y[:, None] * M[:, 6:9] - M[:, 3:6]
+        p = np.cross(a, b)
+        u, vv = p[:, 0] / p[:, 2], p[:, 1] / p[:, 2]
+        assert np.abs(rho / (u * u + vv * vv) - 1).max() <= 1e-4
+        zref = M[:, 6] * u + M[:, 7] * vv + M[:, 8]
+        assert np.abs(zf / zref - 1).max() <= 1e-5
+    # low-pass flag: equal wherever the two branches are not within rounding at that sample
+    assert np.mean((fl & 32) != (po["flags"] & 32)) <= 1e-3
+
+
+def test_bin_sort_bit_exact(tiny):
+    eng = tiny["eng"]
+    P = fetch_proj(eng)
+    ranges, ids = fetch_bins(eng)
+    depth32 = P["rec"][0, :, 11].astype(np.float32)
+    off, oids = oracle.bin_tiles(P["rect"][0], depth32, tiny["cam"].width, tiny["cam"].height)
+    assert np.array_equal(ranges, off)
+    assert np.array_equal(ids, oids)
+    assert int(eng.needed.item()) == len(oids)
+    assert int(eng.status.item()) == 0
+
+
+def test_render_fwd_matches_oracle(tiny):
+    gi = fetch_img(tiny["eng"])
+    io = tiny["io"]
+    errs, frac = compare_images(gi, io, io["margin"])
+    ok = io["margin"] >= FRAGILE
+    ranges, ids = fetch_bins(tiny["eng"])
+    # median fragment and last contributor name the same surfels
+    med_g = np.where(gi["med"] == 0xffffffff, -1, ids[np.minimum(gi["med"], len(ids) - 1)])
+    med_o = np.where(io["med"] < 0, -1, tiny["ids"][np.maximum(io["med"], 0)])
+    assert np.array_equal(med_g[ok], med_o[ok])
+    H, W = gi["alpha"].shape
+    tile = (np.arange(H)[:, None] // 16) * ((W + 15) // 16) + np.arange(W)[None, :] // 16
+    start_g, start_o = ranges[tile], tiny["off"][tile]
+    lg = np.where(gi["last"] > start_g, ids[np.maximum(gi["last"] - 1, 0)], -1)
+    lo = np.where(io["last"] > start_o, tiny["ids"][np.maximum(io["last"] - 1, 0)], -1)
+    assert np.array_equal(lg[ok], lo[ok])
+    # invariants on every pixel
+    assert np.all(gi["T"] >= 1e-4 * (1 - 1e-6)) and np.all(gi["T"] <= 1)
+    assert np.abs(gi["alpha"] + gi["T"] - 1).max() <= 1e-6
+
+
+def test_work_counters_match_oracle(tiny):
+    eng = tiny["eng"]
+    n_eval, n_con, n_bwd = eng.count(tiny["cs"])
+    io = tiny["io"]
+    # exact when no decision is fragile; allow the fragile pixels' worth of slack
+    nfr = int((io["margin"] < FRAGILE).sum())
+    assert abs(n_con - io["n_con"]) <= 4 * nfr + 0
+    assert abs(n_eval - io["n_eval"]) <= 64 * nfr + 0
+
+
+def test_loss_matches_oracle(tiny, cuda):
+    import torch
+    eng = tiny["eng"]
+    img = tiny["io"]["rgb"].astype(np.float32)
+    tgt = tiny["tgt"]
+    lv = eng.loss(torch.from_numpy(tgt).to(cuda)[None], img=torch.from_numpy(img).to(cuda)[None].contiguous())
+    torch.cuda.synchronize()
+    ref = oracle.ssim_loss(img.astype(np.float64), tgt)
+    lv = lv.cpu().numpy()[0]
+    assert abs(lv[0] - ref["loss"]) <= 1e-6 * max(1, abs(ref["loss"])) + 2e-7
+    assert abs(lv[2] - ref["ssim"]) <= 2e-6
+    dt = eng.d_img[0].cpu().numpy()
+    ds = eng.d_img_ssim[0].cpu().numpy()
+    assert np.abs(dt - ref["d_total"]).max() <= 1e-4 * np.abs(ref["d_total"]).max()
+    assert np.abs(ds - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
+
+
+def _upstream(tiny, seed=3):
+    io = tiny["io"]
+    H, W = io["alpha"].shape
+    rng = np.random.default_rng(seed)
+    ok = (io["margin"] >= FRAGILE).astype(np.float64)
+    lo = oracle.ssim_loss(io["rgb"], tiny["tgt"])
+    up = dict(d_rgb=lo["d_total"] * ok, d_rgb_ssim=lo["d_ssim"] * ok,
+              d_depth=rng.normal(size=(H, W)) * 1e-5 * ok, d_depth_med=rng.normal(size=(H, W)) * 1e-5 * ok,
+              d_normal=rng.normal(size=(3, H, W)) * 1e-4 * ok, d_alpha=rng.normal(size=(H, W)) * 1e-4 * ok)
+    return {k: v.astype(np.float32) for k, v in up.items()}
+
+
+def test_render_bwd_matches_oracle(tiny, cuda):
+    import torch
+    from paper_2411_00771_amd import raster
+    eng, params, cs = tiny["eng"], tiny["params"], tiny["cs"]
+    eng.forward(params, cs)
+    up = _upstream(tiny)
+    g = raster.Grads(params, 1)
+    t = {k: torch.from_numpy(v).to(cuda)[None].contiguous() for k, v in up.items()}
+    eng.backward(params, cs, g, **t)
+    torch.cuda.synchronize()
+    ref = oracle.backward_view(tiny["sc"], tiny["cam"], tiny["po"], tiny["off"], tiny["ids"],
+                               {k: v.astype(np.float64) for k, v in up.items()})
+    rp = ref["params"]
+    grad_close("mean", g.mean.cpu().numpy(), rp["mean"])
+    grad_close("log_scale", g.log_scale.cpu().numpy(), rp["log_scale"])
+    grad_close("quat", g.quat.cpu().numpy(), rp["quat"])
+    grad_close("opacity_logit", g.opacity_logit.cpu().numpy(), rp["opacity_logit"])
+    grad_close("sh", g.sh.cpu().numpy(), rp["sh"])
+    grad_close("g_view_total", g.g_view_total[0].cpu().numpy().T, ref["g_total"])
+    grad_close("g_view_ssim", g.g_view_ssim[0].cpu().numpy().T, ref["g_ssim"])
+
+
+def test_densify_matches_oracle(tiny, cuda):
+    import torch
+    from paper_2411_00771_amd import raster
+    eng, params, cs = tiny["eng"], tiny["params"], tiny["cs"]
+    eng.forward(params, cs)
+    up = _upstream(tiny, seed=5)
+    g = raster.Grads(params, 1)
+    t = {k: torch.from_numpy(v).to(cuda)[None].contiguous() for k, v in up.items()}
+    eng.backward(params, cs, g, **t)
+    st = raster.DensifyState(params.n)
+    ost = oracle.new_densify_state(params.n)
+    P = fetch_proj(eng)
+    vis = (P["flags"][0] & 1) > 0
+    lp = (P["flags"][0] & 32) > 0
+    for call in range(2):
+        eng.densify(params, g, st, omega=0.9, eta_min=0.05, grad_threshold=2e-6)
+        torch.cuda.synchronize()
+        gt = g.g_view_total[0].cpu().numpy().T.astype(np.float64)
+        gs = g.g_view_ssim[0].cpu().numpy().T.astype(np.float64)
+        r = oracle.densify_stats(gt, gs, vis, P["radius"][0], tiny["sc"].log_scale, ost, 0.9, 0.05, 2e-6, lowpass=lp)
+        assert abs(st.scale[0].item() / r["scale"] - 1) <= 1e-6
+        assert np.allclose(st.accum_dgd.cpu().numpy(), ost["accum_dgd"], rtol=1e-5, atol=1e-12)
+        assert np.allclose(st.accum_total.cpu().numpy(), ost["accum_total"], rtol=1e-5, atol=1e-12)
+        assert np.array_equal(st.denom.cpu().numpy(), ost["denom"])
+        assert np.array_equal(st.max_radius.cpu().numpy(), ost["max_radius"].astype(np.float32))
+        avg = ost["accum_dgd"] / np.maximum(ost["denom"], 1)
+        near = np.abs(avg / 2e-6 - 1) < 1e-4
+        m = st.mask.cpu().numpy()
+        assert np.array_equal(m[~near], r["mask"][~near])
+        c = st.counters.cpu().numpy()
+        if not near.any():
+            assert np.array_equal(c[:6], r["counters"][:6])
+
+
+def test_multi_view_batch_equals_single_views(cuda):
+    import torch
+    w = scenes.workload(0)
+    sc = w["scene"]
+    cams = [scenes.tiny_camera(96, 80, dist=d) for d in (2.5, 3.0, 3.5)]
+    for k, c in enumerate(cams):
+        c.R = np.array([[np.cos(0.3 * k), 0, np.sin(0.3 * k)], [0, 1, 0], [-np.sin(0.3 * k), 0, np.cos(0.3 * k)]])
+    engb, _, _ = gpu_forward(sc, cams, capacity=1 << 17)
+    for k, c in enumerate(cams):
+        e1, _, _ = gpu_forward(sc, [c], capacity=1 << 17)
+        a, b = fetch_img(engb, k), fetch_img(e1, 0)
+        for key in ("rgb", "depth", "depth_med", "normal", "alpha", "T", "med"):
+            if key == "med":
+                continue
+            assert np.array_equal(a[key], b[key]), key
+    torch.cuda.synchronize()
+
+
+def test_empty_and_culled(cuda):
+    sc = scenes.tiny_scene(1, 64)
+    cam = scenes.tiny_camera(40, 24)
+    cam.bg = (0.25, 0.5, 0.75)
+    # all behind the camera
+    sc.mean[2] -= 10.0
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1024)
+    P = fetch_proj(eng)
+    assert np.all((P["flags"][0] & 2) > 0)
+    gi = fetch_img(eng)
+    assert int(eng.needed.item()) == 0
+    assert np.allclose(gi["rgb"], np.array(cam.bg, np.float32)[:, None, None])
+    assert np.all(gi["alpha"] == 0)
+    # zero surfels
+    sc0 = scenes.tiny_scene(1, 0)
+    eng0, _, _ = gpu_forward(sc0, [cam], capacity=16)
+    assert int(eng0.needed.item()) == 0
+    assert np.allclose(fetch_img(eng0)["rgb"], np.array(cam.bg, np.float32)[:, None, None])
+    # NaN parameters are culled, not propagated
+    sc2 = scenes.tiny_scene(2, 64)
+    sc2.mean[0, :5] = np.nan
+    sc2.log_scale[0, 5:8] = np.inf
+    eng2, _, _ = gpu_forward(sc2, [cam], capacity=4096)
+    P2 = fetch_proj(eng2)
+    assert np.all((P2["flags"][0][:8] & 16) > 0)
+    assert np.isfinite(fetch_img(eng2)["rgb"]).all()
+
+
+def test_ragged_image_parity(cuda):
+    sc = scenes.tiny_scene(7, 600)
+    cam = scenes.tiny_camera(100, 37)
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1 << 15)
+    po, off, ids, io = oracle.forward_view(sc, cam)
+    compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=2e-3)
+    P = fetch_proj(eng)
+    ranges, gids = fetch_bins(eng)
+    o2, i2 = oracle.bin_tiles(P["rect"][0], P["rec"][0, :, 11].astype(np.float32), cam.width, cam.height)
+    assert np.array_equal(ranges, o2) and np.array_equal(gids, i2)
+
+
+def test_overflow_reports_needed(cuda):
+    import torch
+    sc = scenes.tiny_scene(3, 800)
+    cam = scenes.tiny_camera(64, 64)
+    eng, params, cs = gpu_forward(sc, [cam], capacity=32)
+    assert int(eng.status.item()) == 1
+    po, off, ids, io = oracle.forward_view(sc, cam)
+    K = int(eng.needed.item())
+    assert abs(K - len(ids)) <= 2  # equal unless a bbox edge sits on a tile boundary
+    # render leaves the images untouched while the status is set
+    eng.rgb.fill_(float("nan"))
+    eng.render(cs)
+    torch.cuda.synchronize()
+    assert torch.isnan(eng.rgb).all()
+    # rerun with the reported capacity
+    eng.set_capacity(K)
+    eng.status.zero_()
+    eng.forward(params, cs)
+    torch.cuda.synchronize()
+    assert int(eng.status.item()) == 0
+    compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=2e-3)
+
+
+def test_long_tile_lists_sorted_bit_exact(cuda):
+    # 20,000 surfels stacked over one tile: exercises the 16K-entry LDS sort and the global merge
+    rng = np.random.default_rng(11)
+    n = 20000
+    sc = scenes.tiny_scene(4, n)
+    sc.mean[0] = rng.uniform(-0.02, 0.02, n).astype(np.float32)
+    sc.mean[1] = rng.uniform(-0.02, 0.02, n).astype(np.float32)
+    sc.mean[2] = np.round(rng.uniform(-1, 1, n), 2).astype(np.float32)  # many exact depth ties
+    sc.log_scale[:] = np.float32(np.log(0.004))
+    cam = scenes.tiny_camera(64, 64)
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1 << 18)
+    P = fetch_proj(eng)
+    ranges, ids = fetch_bins(eng)
+    assert (np.diff(ranges).max()) > 16384
+    o2, i2 = oracle.bin_tiles(P["rect"][0], P["rec"][0, :, 11].astype(np.float32), cam.width, cam.height)
+    assert np.array_equal(ranges, o2)
+    assert np.array_equal(ids, i2)
