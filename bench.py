@@ -1,0 +1,337 @@
+#!/usr/bin/env python
+"""Training-step benchmark of the MI355X surfel rasterizer.
+
+Workload: 1 M surfels on a synthetic 1 km^2 aerial city (fBm terrain + 200 box buildings, 5 %
+elongated surfels, SH degree 3), 16 aerial cameras at 1600x1066.  One step = one view's
+project -> bin/sort -> render_fwd -> L1+SSIM loss -> render_bwd (+ chain to parameters) ->
+densify_stats, all through the C ABI on one GPU; steps cycle through the 16 cameras.  The
+target of each view is the render of a perturbed copy of the scene (made before timing).
+
+Prints one JSON line: iterations/s (value), Mpix/s, the per-call split, the roofline of the
+dominant kernel (algorithmic flops from the counted pixel-entry pairs) and the FP64 CPU oracle
+timed on one full view on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed); 78.6 without packed math
+PEAK_FP32_NONPACKED = 78.6
+PEAK_HBM_GBS = 8000.0
+# algorithmic flops per pixel-entry pair (FMA = 2): forward 36 per evaluated + 26 per contributing
+# pair; reverse 42 per walked pair + 150 per contributing pair
+F_FWD_EVAL, F_FWD_CON = 36, 26
+F_BWD_WALK, F_BWD_CON = 42, 150
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2411_00771_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2411_00771_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(scene, cam, target):
+    """The FP64 oracle, as it stands, on one full view of the same workload."""
+    import oracle
+    t0 = time.perf_counter()
+    proj, off, ids, img = oracle.forward_view(scene, cam)
+    lo = oracle.ssim_loss(img["rgb"], target)
+    bw = oracle.backward_view(scene, cam, proj, off, ids, dict(d_rgb=lo["d_total"], d_rgb_ssim=lo["d_ssim"]))
+    st = oracle.new_densify_state(scene.n)
+    oracle.densify_stats(bw["g_total"], bw["g_ssim"], (proj["flags"] & 1) > 0, proj["radius"], scene.log_scale, st)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    return dict(value=1.0 / dt, unit="iters/s", cores=cores, kind="oracle",
+                sample=f"one full 1600x1066 view of the 1M-surfel scene (fwd+loss+bwd, both view-space "
+                       f"gradients, densify), {dt:.1f} s")
+
+
+def bench_batched(steps, warmup, n=None):
+    """Differentiation form: 8 views per launch through the autograd Functions at 4 M surfels, against the
+    plain single-view path over the same 8 views on the same scene."""
+    import torch
+    from paper_2411_00771_amd import raster, scenes
+    w = scenes.workload(2, n_override=n)
+    sc, cams_all = w["scene"], w["cameras"]
+    V = len(cams_all)
+    dev = torch.device("cuda:0")
+    params = raster.Params.from_scene(sc, dev)
+    W, H = cams_all[0].width, cams_all[0].height
+    eng = raster.Engine(sc.n, W, H, V)
+    cs = eng.cams(cams_all)
+    need = eng.fit_capacity(params, cs)
+    eng.set_capacity(int(need * 1.25) + 4096)
+    tp = raster.Params.from_scene(scenes.perturbed(sc, 77), dev)
+    eng.forward(tp, cs)
+    target = eng.rgb.clone()
+    del tp
+    leaves = [t.clone().requires_grad_(True) for t in (params.mean, params.log_scale, params.quat,
+                                                       params.opacity_logit, params.sh)]
+    state = raster.DensifyState(sc.n, V)
+
+    def step():
+        for t in leaves:
+            t.grad = None
+        out = raster.rasterize(leaves, eng, cs, sc.sh_degree)
+        loss = raster.L1SSIMLoss.apply(out[0], target, eng, 0.2)
+        loss.backward()
+        eng.densify(params, eng.grads, state)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    assert eng.status.item() == 0
+    # plain single-view path over the same views
+    e1v = raster.Engine(sc.n, W, H, 1)
+    c1 = [e1v.cams([c]) for c in cams_all]
+    need1 = max(e1v.fit_capacity(params, c) for c in c1)
+    e1v.set_capacity(int(need1 * 1.25) + 4096)
+    g1 = raster.Grads(params, 1)
+    st1 = raster.DensifyState(sc.n)
+
+    def step1():
+        for v, c in enumerate(c1):
+            e1v.forward(params, c)
+            e1v.loss(target[v:v + 1].contiguous())
+            e1v.backward(params, c, g1, d_rgb=e1v.d_img, d_rgb_ssim=e1v.d_img_ssim)
+            e1v.densify(params, g1, st1)
+
+    for _ in range(max(1, warmup // 2)):
+        step1()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step1()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / steps
+    assert e1v.status.item() == 0
+    return {"workload": w["name"], "surfels": sc.n, "views_per_launch": V,
+            "batched_views_per_s": round(V * 1e3 / ms_b, 2), "plain_views_per_s": round(V * 1e3 / ms_p, 2),
+            "batched_ms_per_step": round(ms_b, 3), "plain_ms_per_8_views": round(ms_p, 3),
+            "speedup": round(ms_p / ms_b, 3), "steps": steps}
+
+
+def bench_serving(seconds, warmup_s, slots, n=None):
+    """Serving form: Poisson requests (200/s) of mixed resolutions against 5 M resident surfels."""
+    import torch
+    from paper_2411_00771_amd import raster, scenes, server
+    w = scenes.workload(3, n_override=n)
+    sc, city = w["scene"], w["city"]
+    params = raster.Params.from_scene(sc, torch.device("cuda:0"))
+    reqs = [r for r in w["requests"] if r[0] < seconds]
+    rng = np.random.default_rng(3004)
+    cams = [scenes.orbit_camera(rng, city, *scenes.SERVE_RESOLUTIONS[k]) for _, k in reqs]
+    arrivals = [t for t, _ in reqs]
+    out = {}
+    for name, ns in (("continuous", slots), ("plain_queue", 1)):
+        srv = server.Server(params, max_slots=ns, arena_bytes=32 << 30, intersections_per_pixel=3.0)
+        # warm the allocator and the kernels
+        for c in cams[:8]:
+            srv.render_alone(c)
+        srv.finished.clear()
+        dur = seconds if name == "continuous" else min(seconds, 10.0)
+        k = sum(1 for t in arrivals if t < dur)
+        done, wall = server.run_trace(srv, cams[:k], arrivals[:k])
+        lat = np.array([r.latency for r in done if r.arrival - done[0].arrival >= warmup_s and r.error is None])
+        t_first = min(r.arrival for r in done)
+        win = [r for r in done if r.arrival - t_first >= warmup_s]
+        px = sum(r.cam.width * r.cam.height for r in win)
+        span = max(r.done_t for r in win) - min(r.arrival for r in win)
+        out[name] = {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "mpix_per_s": round(px / span / 1e6, 2), "slots": ns, "seconds": dur,
+                     "readmitted": sum(r.tries for r in done)}
+        log(f"[bench] serving {name}: {out[name]}")
+    offered = sum(scenes.SERVE_RESOLUTIONS[k][0] * scenes.SERVE_RESOLUTIONS[k][1] for _, k in reqs) / seconds
+    out.update(workload=w["name"], surfels=sc.n, rate_per_s=200, offered_mpix_per_s=round(offered / 1e6, 1),
+               warmup_s=warmup_s)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=320)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--n", type=int, default=None, help="surfel count override (default 1,000,000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown-steps", type=int, default=32)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this rasterizer build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2411_00771_amd import raster, scenes
+
+    t0 = time.time()
+    w = scenes.workload(1, n_override=args.n)
+    sc, cams_all = w["scene"], w["cameras"]
+    log(f"[bench] workload {w['name']}: n={sc.n}, {len(cams_all)} cameras, generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    params = raster.Params.from_scene(sc, dev)
+    W, H = cams_all[0].width, cams_all[0].height
+    eng = raster.Engine(sc.n, W, H, 1)
+    cams = [eng.cams([c]) for c in cams_all]
+
+    # capacity from the largest view, then targets (renders of a perturbed copy), outside timing
+    need = max(eng.fit_capacity(params, c) for c in cams)
+    eng.set_capacity(int(need * 1.25) + 4096)
+    eng.status.zero_()
+    tp = raster.Params.from_scene(scenes.perturbed(sc, 77), dev)
+    targets = []
+    for c in cams:
+        eng.forward(tp, c)
+        targets.append(eng.rgb.clone())
+    del tp
+    counts = []
+    for c in cams:
+        eng.forward(params, c)
+        counts.append(eng.count(c))
+    torch.cuda.synchronize()
+    log(f"[bench] max intersections {need}, capacity {eng.capacity}; setup {time.time() - t0:.1f}s")
+
+    grads = raster.Grads(params, 1)
+    state = raster.DensifyState(sc.n)
+
+    def step(k, ev=None):
+        c = cams[k % len(cams)]
+        if ev is not None:
+            ev[0].record()
+        eng.project(params, c)
+        if ev is not None:
+            ev[1].record()
+        eng.bin_sort(c)
+        if ev is not None:
+            ev[2].record()
+        eng.render(c)
+        if ev is not None:
+            ev[3].record()
+        eng.loss(targets[k % len(cams)])
+        if ev is not None:
+            ev[4].record()
+        eng.backward(params, c, grads, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
+        if ev is not None:
+            ev[5].record()
+        eng.densify(params, grads, state)
+        if ev is not None:
+            ev[6].record()
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} steps done")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        step(k)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    if eng.status.item() != 0:
+        raise RuntimeError("intersection capacity overflowed during the timed region; result invalid")
+    log(f"[bench] timed {args.steps} steps: {ms:.2f} ms")
+
+    # per-call split with events between the calls (separate pass)
+    names = ["project", "bin_sort", "render_fwd", "loss", "render_bwd", "densify"]
+    tot = np.zeros(len(names))
+    per_fwd, per_bwd = [], []
+    for k in range(args.breakdown_steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        step(k, ev)
+        torch.cuda.synchronize()
+        d = [ev[i].elapsed_time(ev[i + 1]) for i in range(6)]
+        tot += d
+        per_fwd.append((k % len(cams), d[2]))
+        per_bwd.append((k % len(cams), d[4]))
+    split = {nm: tot[i] / args.breakdown_steps for i, nm in enumerate(names)}
+    log("[bench] split (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in split.items()))
+
+    # roofline of the dominant kernel; flops from the counted pairs of each timed view
+    f_fwd = sum(F_FWD_EVAL * counts[v][0] + F_FWD_CON * counts[v][1] for v, _ in per_fwd)
+    t_fwd = sum(t for _, t in per_fwd) * 1e-3
+    f_bwd = sum(F_BWD_WALK * counts[v][2] + F_BWD_CON * counts[v][1] for v, _ in per_bwd)
+    t_bwd = sum(t for _, t in per_bwd) * 1e-3
+    dom = "render_bwd" if split["render_bwd"] >= split["render_fwd"] else "render_fwd"
+    ach = (f_bwd / t_bwd if dom == "render_bwd" else f_fwd / t_fwd) / 1e12
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        tj = json.load(open(tf))
+        if tj.get("kernel_hash") == kernel_hash() and dom in tj.get("bytes_per_launch", {}):
+            traffic = tj["bytes_per_launch"][dom]
+    roof = dict(bound="alu", kernel=dom, achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP32_TFLOPS, 4), frac_nonpacked=round(ach / PEAK_FP32_NONPACKED, 4),
+                traffic=traffic, render_fwd_tflops=round(f_fwd / t_fwd / 1e12, 3),
+                render_bwd_tflops=round(f_bwd / t_bwd / 1e12, 3))
+
+    ips = args.steps / (ms * 1e-3)
+    mean_counts = np.mean(np.array(counts, np.float64), 0)
+    out = {
+        "metric": "fwd+bwd iters/s (1M surfels, 1600x1066)",
+        "value": round(ips, 2),
+        "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"], "surfels": sc.n, "width": W, "height": H, "views": len(cams),
+                   "sh_degree": sc.sh_degree, "step": "project+bin_sort+render_fwd+loss+render_bwd+densify"},
+        "mpix_per_s": round(ips * W * H / 1e6, 2),
+        "split_ms": {k: round(v, 4) for k, v in split.items()},
+        "pairs_per_view": {"evaluated": int(mean_counts[0]), "contributing": int(mean_counts[1]),
+                           "reverse_walked": int(mean_counts[2])},
+        "intersections_max": int(need),
+        "roofline": roof,
+    }
+    target0 = targets[0][0].cpu().numpy().astype(np.float64)
+    del eng, grads, state, params, targets
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("[bench] batched differentiation form (8 views per launch, 4M surfels)")
+        out["batched"] = bench_batched(args.batched_steps, 2)
+        log(f"[bench] batched: {out['batched']}")
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("[bench] serving form (5M surfels, Poisson 200/s, mixed resolutions)")
+        out["serving"] = bench_serving(args.serve_seconds, 2.0, args.serve_slots)
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on one view (CPU)")
+        out["cpu_baseline"] = cpu_baseline(sc, cams_all[0], target0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,12 +82,17 @@ typedef struct {
  *   11   z_c            centre depth (sort key); intersection depth = z_c w0 / w
  *   12   opacity        13-15 rgb   16-18 camera-space normal (facing the camera)   19 k^2 cutoff
  * rect[V][n][4] = tx0, ty0, tx1, ty1 (end exclusive; all 0 when not visible); radius[V][n] screen
- * radius in pixels; flags[V][n] CGV2_F_* bits (written for every surfel). */
+ * radius in pixels; flags[V][n] CGV2_F_* bits (written for every surfel).
+ * visible[V * n], visible_start[V + 1]: written by cgv2_bin_sort; entries visible[visible_start[v] ..
+ * visible_start[v + 1]) are the ids of the surfels visible in view v, ascending (the reverse pass walks
+ * these lists instead of all n surfels). */
 typedef struct {
   float* rec;
   uint16_t* rect;
   float* radius;
   uint8_t* flags;
+  uint32_t* visible;
+  uint32_t* visible_start;
 } cgv2_proj;
 
 /* Tile bins.  ranges[V * tiles + 1]: list of tile t in view v is ids[ranges[v*tiles + t] ..
@@ -160,12 +165,14 @@ typedef struct {
  * Errors: CGV2_EINVAL (nulls, bad sizes), CGV2_EHIP. */
 int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* hip_stream);
 
-/* Workspace bytes for cgv2_bin_sort with the given capacity, view count and tiles per view. */
-size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view);
+/* Workspace bytes for cgv2_bin_sort with the given capacity, view count, tiles per view and surfel
+ * count (0 for invalid arguments). */
+size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view, int64_t n);
 
-/* Tile binning: counts intersections per tile, prefix-sums them into ranges, scatters
- * (depth bits, id) keys and sorts every tile's list; depth ties are broken by id, so the order
- * is deterministic and bit-exact.  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+/* Tile binning: prefix-sums every surfel's tile count, stages (tile, depth bits, id) per surfel,
+ * prefix-sums the per-tile counts into ranges, places the keys in their tiles and sorts every tile's
+ * list; depth ties are broken by id, so the order is deterministic and bit-exact.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
 int cgv2_bin_sort(const cgv2_proj* proj, const cgv2_camera* cams, int32_t V, int64_t n, cgv2_bins* bins,
                   void* workspace, size_t ws_bytes, void* hip_stream);
 

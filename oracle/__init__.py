@@ -156,7 +156,8 @@ def render_brute(proj, cam):
     return out
 
 
-def render_bwd(proj, cam, offsets, ids, d_rgb=None, d_depth=None, d_depth_med=None, d_normal=None, d_alpha=None):
+def render_bwd(proj, cam, offsets, ids, d_rgb=None, d_depth=None, d_depth_med=None, d_normal=None, d_alpha=None,
+               tile_mask=None):
     n = proj["M"].shape[0]
     g = dict(M=np.zeros((n, 9)), rgb=np.zeros((n, 3)), normal=np.zeros((n, 3)), opacity=np.zeros(n))
     counters = np.zeros(1, np.int64)
@@ -164,7 +165,8 @@ def render_bwd(proj, cam, offsets, ids, d_rgb=None, d_depth=None, d_depth_med=No
     lib().orc_render_bwd(ctypes.c_int64(n), _p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]), _p(proj["opacity"]),
                          _p(_d(cam.as_array())), _p(np.ascontiguousarray(offsets, np.int64)),
                          _p(np.ascontiguousarray(ids, np.int32)), *[_p(a) for a in up], _p(g["M"]), _p(g["rgb"]),
-                         _p(g["normal"]), _p(g["opacity"]), _p(counters))
+                         _p(g["normal"]), _p(g["opacity"]), _p(counters),
+                         None if tile_mask is None else _p(np.ascontiguousarray(tile_mask, np.uint8)))
     g["n_pairs"] = int(counters[0])
     return g
 

@@ -290,8 +290,6 @@ void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const 
   double margin = INFINITY;
   uint64_t sig = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
-  uint32_t prev_bits = 0;
-  bool have_prev = false;
   Eval e;
   for (int64_t k = start; k < end; ++k) {
     const int64_t n = id_of(k);
@@ -306,10 +304,6 @@ void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const 
     margin = std::min(margin, relmargin(e.araw, kAlphaMax));
     if (std::isfinite(e.rho3)) margin = std::min(margin, std::fabs(e.rho3 - e.rho2) / std::max(e.rho3, e.rho2));
     margin = std::min(margin, 0.1 * relmargin(T, 0.5));
-    const uint32_t zb = f32bits(M[9 * n + 8]);
-    if (have_prev && (zb > prev_bits ? zb - prev_bits : prev_bits - zb) <= 2) margin = 0;
-    prev_bits = zb;
-    have_prev = true;
     mix((uint64_t)n * 4 + (e.is3d ? 1 : 0) + (e.clamped ? 2 : 0));
     const double w = e.alpha * T;
     for (int c = 0; c < 3; ++c) { C[c] += w * rgb[3 * n + c]; N[c] += w * nrm[3 * n + c]; }
@@ -548,12 +542,14 @@ int orc_render_brute(int64_t n, const double* M, const double* rgb, const double
 // d_dmed, d_normal[3][H][W], d_alpha.  Accumulates (+=) into dM[n][9], d_rgb_s[n][3],
 // d_nrm_s[n][3], d_opac[n].  Fragments are stored per pixel; T_i is the product of the
 // preceding (1 - alpha), never recovered by division.  counters[0] += (pixel, entry) pairs
-// between each pixel's list start and its 'last'.
+// between each pixel's list start and its 'last'.  tile_mask (nullable): only pixels of tiles with
+// a non-zero entry are processed (used to time the oracle on a sample of tiles).
 // ------------------------------------------------------------------------------------------
 int orc_render_bwd(int64_t n, const double* M, const double* rgb, const double* nrm, const double* opac,
                    const double* camv, const int64_t* offsets, const int32_t* ids, const double* d_rgb,
                    const double* d_depth, const double* d_dmed, const double* d_normal, const double* d_alpha,
-                   double* dM, double* d_rgb_s, double* d_nrm_s, double* d_opac, int64_t* counters) {
+                   double* dM, double* d_rgb_s, double* d_nrm_s, double* d_opac, int64_t* counters,
+                   const uint8_t* tile_mask) {
   const Cam cam = load_cam(camv);
   const int tx = (cam.W + kTile - 1) / kTile;
   const int64_t HW = (int64_t)cam.W * cam.H;
@@ -583,6 +579,7 @@ int orc_render_bwd(int64_t n, const double* M, const double* rgb, const double* 
       for (int i = 0; i < cam.W; ++i) {
         const int64_t p = (int64_t)j * cam.W + i;
         const int64_t t = (int64_t)(j / kTile) * tx + i / kTile;
+        if (tile_mask && !tile_mask[t]) continue;
         const double x = i + 0.5, y = j + 0.5;
         // forward, storing contributing fragments
         fr.clear();

@@ -35,7 +35,7 @@ class Surfels(ctypes.Structure):
 
 
 class Proj(ctypes.Structure):
-    _fields_ = [("rec", P), ("rect", P), ("radius", P), ("flags", P)]
+    _fields_ = [("rec", P), ("rect", P), ("radius", P), ("flags", P), ("visible", P), ("visible_start", P)]
 
 
 class Bins(ctypes.Structure):
@@ -84,7 +84,7 @@ def lib():
     i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "cgv2_project": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Camera), i32, ctypes.POINTER(Proj), P]),
-        "cgv2_bin_sort_workspace": (sz, [i64, i32, i32]),
+        "cgv2_bin_sort_workspace": (sz, [i64, i32, i32, i64]),
         "cgv2_bin_sort": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Camera), i32, i64, ctypes.POINTER(Bins),
                                          P, sz, P]),
         "cgv2_render_fwd": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Bins), ctypes.POINTER(Camera), i32, i64,

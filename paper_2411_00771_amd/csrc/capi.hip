@@ -31,7 +31,9 @@ bool surfels_ok(const cgv2_surfels* s) {
          (s->n == 0 || (s->mean && s->log_scale && s->quat && s->opacity_logit && s->sh));
 }
 
-bool proj_ok(const cgv2_proj* p) { return p && p->rec && p->rect && p->radius && p->flags; }
+bool proj_ok(const cgv2_proj* p) {
+  return p && p->rec && p->rect && p->radius && p->flags && p->visible && p->visible_start;
+}
 
 bool bins_ok(const cgv2_bins* b) {
   return b && b->capacity >= 0 && b->capacity < (int64_t)0xffffffff && b->ranges && b->status && b->needed &&
@@ -86,19 +88,20 @@ int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2
   return CGV2_OK;
 }
 
-size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view) {
-  if (capacity < 0 || V < 1 || tiles_per_view < 1) return 0;
-  size_t off[7];
-  return cgv2_binsort_ws_layout(capacity, V, tiles_per_view, off);
+size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view, int64_t n) {
+  if (capacity < 0 || V < 1 || tiles_per_view < 1 || n < 0) return 0;
+  size_t off[9];
+  return cgv2_binsort_ws_layout(capacity, V, tiles_per_view, n, off);
 }
 
 int cgv2_bin_sort(const cgv2_proj* proj, const cgv2_camera* cams, int32_t V, int64_t n, cgv2_bins* bins,
                   void* workspace, size_t ws_bytes, void* stream) {
-  if (!cams_ok(cams, V) || !proj || !proj->rect || !proj->rec || !bins_ok(bins) || n < 0 || !workspace)
+  if (!cams_ok(cams, V) || !proj_ok(proj) || !bins_ok(bins) || n < 0 || !workspace)
     return CGV2_EINVAL;
+  if ((int64_t)V * n >= (int64_t)0xffffffff) return CGV2_EINVAL;
   const int tx = tiles_x(cams), ty = tiles_y(cams);
   if ((int64_t)V * tx * ty >= (int64_t)0x7fffffff) return CGV2_EINVAL;
-  if (ws_bytes < cgv2_bin_sort_workspace(bins->capacity, V, tx * ty)) return CGV2_EWORKSPACE;
+  if (ws_bytes < cgv2_bin_sort_workspace(bins->capacity, V, tx * ty, n)) return CGV2_EWORKSPACE;
   return hip_status(cgv2_launch_bin_sort(*proj, n, V, tx, ty, *bins, workspace, (hipStream_t)stream));
 }
 
@@ -164,7 +167,7 @@ int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bin
     int rc = hip_status(cgv2_launch_render_bwd(*proj, *bins, pack(cams, v0, cnt), s->n, tx, ty, *img, *up, rg,
                                                (hipStream_t)stream));
     if (rc) return rc;
-    rc = hip_status(cgv2_launch_project_bwd(*s, pack(cams, v0, cnt), proj->flags, rg, *g, (hipStream_t)stream));
+    rc = hip_status(cgv2_launch_project_bwd(*s, pack(cams, v0, cnt), *proj, rg, *g, (hipStream_t)stream));
     if (rc) return rc;
   }
   return CGV2_OK;

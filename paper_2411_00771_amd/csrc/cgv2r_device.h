@@ -17,10 +17,11 @@ enum : int {
   R_ZC, R_OP, R_R, R_G, R_B, R_NX, R_NY, R_NZ, R_K2
 };
 
-// record-gradient field offsets ([V][kGradFields][n] in the backward workspace)
+// record-gradient field offsets ([V][kGradFields][n] in the backward workspace); the first 16 are the
+// slots of the wave reduce-scatter in the reverse pass
 enum : int {
-  G_CX = 0, G_CY, G_A11, G_A12, G_A21, G_A22, G_W0, G_W1, G_W2, G_ZC, G_OP,
-  G_R, G_G, G_B, G_NX, G_NY, G_NZ, G_SCX, G_SCY
+  G_CX = 0, G_CY, G_A11, G_A12, G_A21, G_A22, G_W0, G_W1, G_W2, G_OP, G_R, G_G, G_B, G_SCX, G_SCY, G_ZC,
+  G_NX, G_NY, G_NZ
 };
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
@@ -41,41 +42,69 @@ struct CamPack {
   int v0, count;
 };
 
-// Per-pixel evaluation of one surfel, shared by the forward and the backward kernels so that
-// both take bit-identical decisions.  (xr, yr) = pixel sample minus the projected centre.
-struct PairEval {
-  float P1, P2, w, nn, ww, rho, G, araw, alpha;
-  bool is3d;
-};
-
-__device__ __forceinline__ void eval_pair(float xr, float yr, float a11, float a12, float a21, float a22, float w0,
-                                          float w1, float w2, float op, PairEval& e) {
-  e.P1 = fmaf(a11, xr, a12 * yr);
-  e.P2 = fmaf(a21, xr, a22 * yr);
-  e.w = fmaf(w1, xr, fmaf(w2, yr, w0));
-  e.nn = fmaf(e.P1, e.P1, e.P2 * e.P2);
-  e.ww = e.w * e.w;
-  const float rho2 = 2.0f * fmaf(xr, xr, yr * yr);
-  // rho_3d = nn / ww <= rho_2d, evaluated without a division; ww == 0 means the ray is parallel
-  // to the plane (rho_3d infinite)
-  e.is3d = (e.ww > 0.0f) && (e.nn <= rho2 * e.ww);
-  e.rho = e.is3d ? e.nn * __builtin_amdgcn_rcpf(e.ww) : rho2;
-  e.G = exp2f(e.rho * kNegHalfLog2e);
-  e.araw = op * e.G;
-  e.alpha = fminf(kAlphaMax, e.araw);
-}
-
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Sum over the 64 lanes of a wave; the result is valid in every lane.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
+// DPP move (gfx9 encodings); lanes of rows outside kRowMask receive 0.
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave with DPP row operations only (no LDS traffic); the total is
+// valid in lane 63.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);       // row_half_mirror: 4-lane groups -> 8
+  v += dpp<0x140>(v);       // row_mirror: 8 -> 16 (every lane holds its row's sum)
+  v += dpp<0x142, 0xa>(v);  // row_bcast:15 -> rows 1 and 3 add rows 0 and 2
+  v += dpp<0x143, 0xc>(v);  // row_bcast:31 -> rows 2 and 3 add rows 0+1
   return v;
+}
+
+// Reduce-scatter of 16 per-lane values over a wave: on return every lane holds the wave total of
+// value index reduce16_index(lane).  Exchanges: xor 32 and xor 16 with the gfx950 row-swap
+// instructions (x' + y' after a swap is already the pairwise sum of the kept half), xor 1 and xor 2
+// with DPP quad permutations, then an all-reduce over lane bits 2-3 with two row rotations.
+// About 35 VALU operations for 16 values, against 96 for 16 separate reductions.
+__device__ __forceinline__ int reduce16_index(int lane) {
+  return ((lane >> 1) & 1) | ((lane & 1) << 1) | (((lane >> 4) & 1) << 2) | (((lane >> 5) & 1) << 3);
+}
+
+__device__ __forceinline__ float reduce16_scatter(float (&v)[16]) {
+  const int lane = (int)(threadIdx.x & 63u);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 8]), false, false);
+    v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 4]), false, false);
+    v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool b0 = lane & 1, b1 = lane & 2;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float send = b0 ? v[j] : v[j + 2];
+    const float keep = b0 ? v[j + 2] : v[j];
+    v[j] = keep + dpp<0xB1>(send);
+  }
+  float t;
+  {
+    const float send = b1 ? v[0] : v[1];
+    const float keep = b1 ? v[1] : v[0];
+    t = keep + dpp<0x4E>(send);
+  }
+  t += dpp<0x124>(t);  // row_ror:4
+  t += dpp<0x128>(t);  // row_ror:8
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
 }
 
 // Block -> tile mapping that keeps neighbouring tiles on one XCD: hardware dispatches

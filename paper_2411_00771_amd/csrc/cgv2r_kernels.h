@@ -8,10 +8,10 @@
 #include "cgv2r_device.h"
 
 hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st);
-hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const uint8_t* flags,
+hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const float* rg, const cgv2_grads& g, hipStream_t st);
 
-size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, size_t* off);
+size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
                                 void* ws, hipStream_t st);
 

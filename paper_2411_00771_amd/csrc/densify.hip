@@ -3,9 +3,9 @@
 //
 // k_dgd_partial  per view, per block of 1024 surfels: sums of |g_total| and |g_ssim| over the
 //                visible surfels, tree-reduced in FP64 in a fixed order
-// k_densify      every block re-reduces the (few) block partials of each view in the same fixed
-//                order, so all blocks agree bit-for-bit on scale_v = max(omega a_tot / a_ssim, 1);
-//                then updates the per-surfel state, the masks and the counters
+// k_dgd_final    one workgroup reduces each view's block partials in a fixed order into
+//                scale_v = max(omega a_tot / a_ssim, 1) (deterministic)
+// k_densify      updates the per-surfel state, the masks and the counters
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
@@ -48,16 +48,10 @@ __global__ __launch_bounds__(kDBlock) void k_dgd_partial(const uint8_t* __restri
   if (blockIdx.x == 0 && v == 0 && threadIdx.x < 8) counters[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8_t* __restrict__ flags,
-                                                     const float* __restrict__ radius, const float* __restrict__ gt,
-                                                     const float* __restrict__ gs, int V, const double* __restrict__ partial,
-                                                     int nblocks, cgv2_densify_params prm, cgv2_densify_state st) {
+__global__ __launch_bounds__(kDBlock) void k_dgd_final(const double* __restrict__ partial, int nblocks, int V,
+                                                       float omega, float* __restrict__ scale_ws,
+                                                       float* __restrict__ scale_out) {
   __shared__ double red[2][kDBlock];
-  __shared__ float scale_s[64];
-  __shared__ uint32_t cnt_s[8];
-  const int64_t n = s.n;
-  if (threadIdx.x < 8) cnt_s[threadIdx.x] = 0;
-  // per-view factor, reduced identically in every block (fixed order)
   for (int v = 0; v < V; ++v) {
     double a = 0, b = 0;
     for (int k = threadIdx.x; k < nblocks; k += kDBlock) {
@@ -76,12 +70,23 @@ __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8
     }
     if (threadIdx.x == 0) {
       const double at = red[0][0], as = red[1][0];
-      const double sc = as > 0 ? fmax((double)prm.omega * at / as, 1.0) : 1.0;
-      scale_s[v & 63] = (float)sc;
-      if (blockIdx.x == 0 && st.scale) st.scale[v] = (float)sc;
+      const float sc = (float)(as > 0 ? fmax((double)omega * at / as, 1.0) : 1.0);
+      scale_ws[v] = sc;
+      if (scale_out) scale_out[v] = sc;
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8_t* __restrict__ flags,
+                                                     const float* __restrict__ radius, const float* __restrict__ gt,
+                                                     const float* __restrict__ gs, int V,
+                                                     const float* __restrict__ scale_ws, cgv2_densify_params prm,
+                                                     cgv2_densify_state st) {
+  __shared__ uint32_t cnt_s[8];
+  const int64_t n = s.n;
+  if (threadIdx.x < 8) cnt_s[threadIdx.x] = 0;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kDBlock + threadIdx.x;
   if (i < n) {
     float adgd = st.accum_dgd[i], atot = st.accum_total[i], mr = st.max_radius[i];
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8
         const float* g2 = gs + (int64_t)v * 2 * n;
         ns = sqrtf(g2[i] * g2[i] + g2[n + i] * g2[n + i]);
       }
-      adgd = fmaf(scale_s[v & 63], ns, adgd);
+      adgd = fmaf(scale_ws[v], ns, adgd);
       atot += nt;
       den += 1;
       mr = fmaxf(mr, radius[vi]);
@@ -132,8 +137,8 @@ __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8
 
 size_t cgv2_densify_ws_layout(int64_t n, int V, size_t* off) {
   const int64_t nb = (n + cgv2::kDBlock * cgv2::kDItems - 1) / (cgv2::kDBlock * cgv2::kDItems);
-  off[0] = 0;
-  return (size_t)(2 * sizeof(double) * (size_t)(nb > 0 ? nb : 1) * V + 255) & ~(size_t)255;
+  off[0] = ((size_t)(2 * sizeof(double) * (size_t)(nb > 0 ? nb : 1) * V + 255) & ~(size_t)255);
+  return off[0] + (((size_t)V * sizeof(float) + 255) & ~(size_t)255);
 }
 
 hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const cgv2_grads& g, int V,
@@ -142,13 +147,18 @@ hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const 
   const int64_t n = s.n;
   const int nb = (int)((n + cgv2::kDBlock * cgv2::kDItems - 1) / (cgv2::kDBlock * cgv2::kDItems));
   const int nbp = nb > 0 ? nb : 1;
+  size_t off[1];
+  cgv2_densify_ws_layout(n, V, off);
   double* partial = (double*)ws;
+  float* scale_ws = (float*)((char*)ws + off[0]);
   hipLaunchKernelGGL(cgv2::k_dgd_partial, dim3((unsigned)nbp, (unsigned)V), dim3(cgv2::kDBlock), 0, stream, p.flags,
                      g.g_view_total, g.g_view_ssim, n, partial, nbp, st.counters);
+  hipLaunchKernelGGL(cgv2::k_dgd_final, dim3(1), dim3(cgv2::kDBlock), 0, stream, partial, nbp, V, prm.omega, scale_ws,
+                     st.scale);
   if (n > 0) {
     hipLaunchKernelGGL(cgv2::k_densify, dim3((unsigned)((n + cgv2::kDBlock - 1) / cgv2::kDBlock)),
                        dim3(cgv2::kDBlock), 0, stream, s, p.flags, p.radius, g.g_view_total, g.g_view_ssim, V,
-                       partial, nbp, prm, st);
+                       scale_ws, prm, st);
   }
   return hipGetLastError();
 }

@@ -8,6 +8,8 @@
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
+#include <algorithm>
+
 namespace cgv2 {
 
 // Real spherical harmonics (Condon-Shortley phase, index l*l + l + m) as polynomials in the unit
@@ -27,7 +29,8 @@ struct SH {
 };
 
 // Y[k] and, if dY != nullptr, the gradient of each polynomial w.r.t. (x, y, z).
-__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y, float (*dY)[3]) {
+template <int deg>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y, float (*dY)[3]) {
   Y[0] = SH::c0;
   if (dY) { dY[0][0] = dY[0][1] = dY[0][2] = 0.f; }
   if (deg < 1) return;
@@ -68,6 +71,48 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
     dY[14][0] = 2.f * SH::c3e * x * z; dY[14][1] = -2.f * SH::c3e * y * z; dY[14][2] = SH::c3e * (xx - yy);
     dY[15][0] = -SH::c3a * (3.f * xx - 3.f * yy); dY[15][1] = SH::c3a * 6.f * x * y; dY[15][2] = 0.f;
   }
+}
+
+// sum_k g[k] grad Y_k(x, y, z): the direction gradient of a weighted SH sum without the per-basis
+// gradient table.
+template <int deg>
+__device__ __forceinline__ void sh_grad_dot(const float* g, float x, float y, float z, float* out) {
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (deg >= 1) {
+    gy -= SH::c1 * g[1];
+    gz += SH::c1 * g[2];
+    gx -= SH::c1 * g[3];
+  }
+  if (deg >= 2) {
+    gx += SH::c2a * y * g[4];
+    gy += SH::c2a * x * g[4];
+    gy -= SH::c2a * z * g[5];
+    gz -= SH::c2a * y * g[5];
+    gz += SH::c2b * 6.f * z * g[6];
+    gx -= SH::c2a * z * g[7];
+    gz -= SH::c2a * x * g[7];
+    gx += 2.f * SH::c2c * x * g[8];
+    gy -= 2.f * SH::c2c * y * g[8];
+  }
+  if (deg >= 3) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx -= SH::c3a * 6.f * x * y * g[9];
+    gy -= SH::c3a * (3.f * xx - 3.f * yy) * g[9];
+    gx += SH::c3b * y * z * g[10];
+    gy += SH::c3b * x * z * g[10];
+    gz += SH::c3b * x * y * g[10];
+    gy -= SH::c3c * (5.f * zz - 1.f) * g[11];
+    gz -= SH::c3c * 10.f * y * z * g[11];
+    gz += SH::c3d * (15.f * zz - 3.f) * g[12];
+    gx -= SH::c3c * (5.f * zz - 1.f) * g[13];
+    gz -= SH::c3c * 10.f * x * z * g[13];
+    gx += 2.f * SH::c3e * x * z * g[14];
+    gy -= 2.f * SH::c3e * y * z * g[14];
+    gz += SH::c3e * (xx - yy) * g[14];
+    gx -= SH::c3a * (3.f * xx - 3.f * yy) * g[15];
+    gy += SH::c3a * 6.f * x * y * g[15];
+  }
+  out[0] = gx; out[1] = gy; out[2] = gz;
 }
 
 struct Geom {
@@ -151,12 +196,11 @@ __device__ __forceinline__ void homography(const double* M, Homog& h) {
   h.scale = m > 0 ? 1.0 / m : 1.0;
 }
 
-__global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, cgv2_proj out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = cams.v0 + (int)blockIdx.y;
+// Projects surfel i into view v; returns whether it is binned (visible).
+template <int DEG>
+__device__ __forceinline__ bool project_one(const cgv2_surfels& s, const DevCam& c, int v, int64_t i,
+                                            const cgv2_proj& out) {
   const int64_t n = s.n;
-  if (i >= n) return;
-  const DevCam& c = cams.c[blockIdx.y];
   const int64_t vi = (int64_t)v * n + i;
   uint16_t* rect = out.rect + 4 * vi;
   Geom g;
@@ -177,7 +221,7 @@ __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, c
     out.flags[vi] = (uint8_t)fl;
     out.radius[vi] = 0.f;
     *(uint2*)rect = make_uint2(0u, 0u);
-    return;
+    return false;
   }
   const double* M = g.M;
   const double ik2 = 1.0 / k2;
@@ -210,7 +254,7 @@ __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, c
   if (!(i0 <= i1 && j0 <= j1)) {
     out.flags[vi] = (uint8_t)fl;
     *(uint2*)rect = make_uint2(0u, 0u);
-    return;
+    return false;
   }
   fl |= CGV2_F_VISIBLE;
   out.flags[vi] = (uint8_t)fl;
@@ -219,12 +263,14 @@ __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, c
   *(uint2*)rect = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
 
   // SH colour
-  const int K = (s.sh_degree + 1) * (s.sh_degree + 1);
-  float Y[16];
-  sh_basis(s.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float Y[K];
+  sh_basis<DEG>(g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
   float col[3];
+#pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     float acc = 0.5f;
+#pragma unroll
     for (int k = 0; k < K; ++k) acc = fmaf(s.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], acc);
     col[ch] = fmaxf(acc, 0.f);
   }
@@ -238,34 +284,38 @@ __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, c
   rp[2] = make_float4((float)(h.W[0] * sc), (float)(h.W[1] * sc), (float)(h.W[2] * sc), (float)M[8]);
   rp[3] = make_float4((float)g.o, col[0], col[1], col[2]);
   rp[4] = make_float4(g.nc[0], g.nc[1], g.nc[2], (float)k2);
+  return true;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, cgv2_proj out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = cams.v0 + (int)blockIdx.y;
+  if (i < s.n) project_one<DEG>(s, cams.c[blockIdx.y], v, i, out);
 }
 
 // ------------------------------------------------------------------------------------------
 // Reverse: record gradients of every view -> parameter gradients (+=), view-space gradients.
 // ------------------------------------------------------------------------------------------
+// One view (cams.c[0], view index cams.v0), one thread per entry of its visible list
+// (list[vstart[0] .. vstart[1])); each surfel appears once per list, so the parameter gradients are
+// added without atomics.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cams,
-                                                      const uint8_t* __restrict__ flags,
+                                                      const uint32_t* __restrict__ list,
+                                                      const uint32_t* __restrict__ vstart,
                                                       const float* __restrict__ rg, cgv2_grads gr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = s.n;
-  if (i >= n) return;
-  const int K = (s.sh_degree + 1) * (s.sh_degree + 1);
+  const uint32_t e0 = vstart[0], e1 = vstart[1];
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  for (uint32_t e = e0 + blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += gridDim.x * blockDim.x) {
+  const int64_t i = list[e];
   double dmu[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dls[2] = {0, 0}, dlogit = 0;
-  float dsh[48];
-  for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
-  bool any = false;
-  for (int lv = 0; lv < cams.count; ++lv) {
-    const int v = cams.v0 + lv;
-    const int64_t vi = (int64_t)v * n + i;
-    const DevCam& c = cams.c[lv];
+  {
+    const int v = cams.v0;
+    const DevCam& c = cams.c[0];
     float* gvt = gr.g_view_total ? gr.g_view_total + (int64_t)v * 2 * n : nullptr;
     float* gvs = gr.g_view_ssim ? gr.g_view_ssim + (int64_t)v * 2 * n : nullptr;
-    if (!(flags[vi] & CGV2_F_VISIBLE)) {
-      if (gvt) { gvt[i] = 0.f; gvt[n + i] = 0.f; }
-      if (gvs) { gvs[i] = 0.f; gvs[n + i] = 0.f; }
-      continue;
-    }
-    any = true;
     const float* r = rg + (int64_t)v * kGradFields * n + i;
     float d[kGradFields];
     for (int k = 0; k < kGradFields; ++k) d[k] = r[(int64_t)k * n];
@@ -335,37 +385,40 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
     dls[0] += dsu * g.su;
     dls[1] += dsv * g.sv;
     dlogit += (double)d[G_OP] * g.o * (1 - g.o);
-    // colour through SH
-    float Y[16], dY[16][3];
-    sh_basis(s.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y, dY);
-    float ddir[3] = {0.f, 0.f, 0.f};
+    // colour through SH: coefficient gradients go to memory per view (+=), the direction
+    // gradient is contracted on the fly
+    float Y[K], gY[K];
+    sh_basis<DEG>(g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
+#pragma unroll
+    for (int k = 0; k < K; ++k) gY[k] = 0.f;
     const float dcol[3] = {d[G_R], d[G_G], d[G_B]};
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float raw = 0.5f;
-      float f[16];
+      float f[K];
+#pragma unroll
       for (int k = 0; k < K; ++k) {
         f[k] = s.sh[(int64_t)(k * 3 + ch) * n + i];
         raw = fmaf(f[k], Y[k], raw);
       }
       if (raw < 0.f) continue;
+#pragma unroll
       for (int k = 0; k < K; ++k) {
-        dsh[k * 3 + ch] = fmaf(dcol[ch], Y[k], dsh[k * 3 + ch]);
-        const float gf = dcol[ch] * f[k];
-        ddir[0] = fmaf(gf, dY[k][0], ddir[0]);
-        ddir[1] = fmaf(gf, dY[k][1], ddir[1]);
-        ddir[2] = fmaf(gf, dY[k][2], ddir[2]);
+        gY[k] = fmaf(dcol[ch], f[k], gY[k]);
+        gr.d_sh[(int64_t)(k * 3 + ch) * n + i] += dcol[ch] * Y[k];
       }
     }
+    float ddir[3];
+    sh_grad_dot<DEG>(gY, g.dir[0], g.dir[1], g.dir[2], ddir);
     const float dd = ddir[0] * g.dir[0] + ddir[1] * g.dir[1] + ddir[2] * g.dir[2];
     for (int k = 0; k < 3; ++k) dmu[k] += (double)((ddir[k] - g.dir[k] * dd) / g.dist);
   }
-  if (!any) return;
   for (int k = 0; k < 3; ++k) gr.d_mean[k * n + i] += (float)dmu[k];
   for (int k = 0; k < 4; ++k) gr.d_quat[k * n + i] += (float)dq[k];
   gr.d_log_scale[i] += (float)dls[0];
   gr.d_log_scale[n + i] += (float)dls[1];
   gr.d_opacity_logit[i] += (float)dlogit;
-  for (int k = 0; k < 3 * K; ++k) gr.d_sh[(int64_t)k * n + i] += dsh[k];
+  }
 }
 
 }  // namespace cgv2
@@ -373,14 +426,41 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
 hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)cams.count);
-  hipLaunchKernelGGL(cgv2::k_project, grid, dim3(256), 0, st, s, cams, p);
+  switch (s.sh_degree) {
+    case 0: hipLaunchKernelGGL(cgv2::k_project<0>, grid, dim3(256), 0, st, s, cams, p); break;
+    case 1: hipLaunchKernelGGL(cgv2::k_project<1>, grid, dim3(256), 0, st, s, cams, p); break;
+    case 2: hipLaunchKernelGGL(cgv2::k_project<2>, grid, dim3(256), 0, st, s, cams, p); break;
+    default: hipLaunchKernelGGL(cgv2::k_project<3>, grid, dim3(256), 0, st, s, cams, p); break;
+  }
   return hipGetLastError();
 }
 
-hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const uint8_t* flags,
+hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const float* rg, const cgv2_grads& g, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cgv2::k_project_bwd, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s, cams, flags, rg,
-                     g);
+  const int64_t n = s.n;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  for (int lv = 0; lv < cams.count; ++lv) {
+    const int v = cams.v0 + lv;
+    cgv2::CamPack one;
+    one.c[0] = cams.c[lv];
+    one.v0 = v;
+    one.count = 1;
+    // g_view rows are overwritten: zero for surfels outside this view's list
+    if (g.g_view_total)
+      hipLaunchKernelGGL(cgv2::k_fill<float>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st,
+                         g.g_view_total + (int64_t)v * 2 * n, 2 * n, 0.f);
+    if (g.g_view_ssim)
+      hipLaunchKernelGGL(cgv2::k_fill<float>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st,
+                         g.g_view_ssim + (int64_t)v * 2 * n, 2 * n, 0.f);
+    const uint32_t* list = p.visible;
+    const uint32_t* cnt = p.visible_start + v;
+    switch (s.sh_degree) {
+      case 0: hipLaunchKernelGGL(cgv2::k_project_bwd<0>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
+      case 1: hipLaunchKernelGGL(cgv2::k_project_bwd<1>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
+      case 2: hipLaunchKernelGGL(cgv2::k_project_bwd<2>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
+      default: hipLaunchKernelGGL(cgv2::k_project_bwd<3>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
+    }
+  }
   return hipGetLastError();
 }

@@ -120,6 +120,8 @@ class Engine:
         self.rect = torch.empty(vn * 4, dtype=torch.int16, device=device)
         self.radius = torch.empty(vn, device=device)
         self.flags = torch.empty(vn, dtype=torch.uint8, device=device)
+        self.visible = torch.empty(vn, dtype=torch.int32, device=device)
+        self.visible_start = torch.zeros(V + 1, dtype=torch.int32, device=device)
         self.ranges = torch.zeros(V * self.tiles + 1, dtype=torch.int32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.needed = torch.zeros(1, dtype=torch.int64, device=device)
@@ -141,7 +143,8 @@ class Engine:
             self.ws_dens = torch.empty(max(L.cgv2_densify_workspace(n, V), 256), dtype=torch.uint8, device=device)
         self.pending_ssim = None
         self.set_capacity(capacity if capacity is not None else max(1 << 20, 16 * n * V))
-        self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags))
+        self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags), ptr(self.visible),
+                               ptr(self.visible_start))
         self._img = _lib.Image(ptr(self.rgb), ptr(self.depth), ptr(self.depth_med), ptr(self.normal),
                                ptr(self.alpha), ptr(self.T_final), ptr(self.last), ptr(self.med))
 
@@ -149,16 +152,29 @@ class Engine:
         L = _lib.lib()
         self.capacity = int(capacity)
         self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
-        self.ws_bin = torch.empty(L.cgv2_bin_sort_workspace(self.capacity, self.V, self.tiles), dtype=torch.uint8,
+        self.ws_bin = torch.empty(L.cgv2_bin_sort_workspace(self.capacity, self.V, self.tiles, self.n), dtype=torch.uint8,
                                   device=self.device)
         self._bins = _lib.Bins(self.capacity, ptr(self.ids), ptr(self.ranges), ptr(self.status), ptr(self.needed))
 
     # ---- the five calls (+ loss) -------------------------------------------------------------
-    def cams(self, cams: Sequence) -> ctypes.Array:
+    def cams(self, cams: Sequence, exact: bool = True) -> ctypes.Array:
+        """C camera array for a call.  exact=False admits any resolution up to the allocated one
+        (all cameras of a call still share one size); outputs then occupy the leading elements."""
         assert len(cams) == self.V
         for c in cams:
-            assert c.width == self.W and c.height == self.H
+            if exact:
+                assert c.width == self.W and c.height == self.H
+            else:
+                assert c.width <= self.W and c.height <= self.H and c.width == cams[0].width \
+                    and c.height == cams[0].height
         return _lib.camera_array(cams)
+
+    def image(self, name: str, width: int, height: int):
+        """The first view's output `name` for a call made at width x height (a view, no copy)."""
+        t = getattr(self, name)
+        per = {"rgb": 3, "normal": 3}.get(name, 1)
+        flat = t.view(-1)[: per * width * height]
+        return flat.view(per, height, width) if per > 1 else flat.view(height, width)
 
     def project(self, params: Params, cams):
         check(_lib.lib().cgv2_project(ctypes.byref(params.struct()), cams, self.V, ctypes.byref(self._proj),
@@ -248,16 +264,14 @@ class Rasterize2DGS(torch.autograd.Function):
     def backward(ctx, d_rgb, d_depth, d_depth_med, d_normal, d_alpha):
         eng: Engine = ctx.engine
         p = ctx.params
-        if getattr(eng, "grads", None) is None or eng.grads.mean.shape != p.mean.shape:
-            eng.grads = Grads(p, eng.V)
-        g = eng.grads
-        g.zero_()
+        # fresh zeroed gradients (the ABI accumulates), handed to autograd without a copy
+        g = Grads(p, eng.V)
+        eng.grads = g
         c = lambda t: None if t is None else t.contiguous()
         eng.backward(p, ctx.cams, g, d_rgb=c(d_rgb), d_depth=c(d_depth), d_depth_med=c(d_depth_med),
                      d_normal=c(d_normal), d_alpha=c(d_alpha), d_rgb_ssim=eng.pending_ssim)
         eng.pending_ssim = None
-        return g.mean.clone(), g.log_scale.clone(), g.quat.clone(), g.opacity_logit.clone(), g.sh.clone(), None, \
-            None, None
+        return g.mean, g.log_scale, g.quat, g.opacity_logit, g.sh, None, None, None
 
 
 class L1SSIMLoss(torch.autograd.Function):

@@ -37,17 +37,18 @@ def test_header_constants_match_binding():
 def test_strerror_and_workspace_sizes():
     L = _lib.lib()
     assert L.cgv2_strerror(0) == b"ok" and L.cgv2_strerror(-2) == b"workspace too small"
-    a = L.cgv2_bin_sort_workspace(1 << 20, 1, 6700)
-    b = L.cgv2_bin_sort_workspace(1 << 21, 1, 6700)
-    assert b - a >= 16 * (1 << 20)  # two u64 arrays per intersection
-    assert L.cgv2_bin_sort_workspace(-1, 1, 10) == 0 and L.cgv2_bin_sort_workspace(10, 0, 10) == 0
+    a = L.cgv2_bin_sort_workspace(1 << 20, 1, 6700, 1000)
+    b = L.cgv2_bin_sort_workspace(1 << 21, 1, 6700, 1000)
+    assert b - a >= 20 * (1 << 20)  # two u64 and one u32 array per intersection
+    assert L.cgv2_bin_sort_workspace(1 << 20, 1, 6700, 10 ** 6) >= a + 4 * (10 ** 6 - 1000)
+    assert L.cgv2_bin_sort_workspace(-1, 1, 10, 5) == 0 and L.cgv2_bin_sort_workspace(10, 0, 10, 5) == 0
     assert L.cgv2_render_bwd_workspace(1000, 2) >= 19 * 4 * 1000 * 2
     assert L.cgv2_loss_workspace(0, 10, 1) == 0
     assert L.cgv2_densify_workspace(10, 1) > 0
 
 
 def _fake_proj():
-    return _lib.Proj(ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), ctypes.c_void_p(1024))
+    return _lib.Proj(*[ctypes.c_void_p(256 * (k + 1)) for k in range(6)])
 
 
 def test_argument_validation_returns_einval():
@@ -99,7 +100,7 @@ def test_small_workspace_returns_eworkspace():
     cam.width, cam.height = 64, 64
     p = _fake_proj()
     bins = _lib.Bins(1000, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256))
-    need = L.cgv2_bin_sort_workspace(1000, 1, 16)
+    need = L.cgv2_bin_sort_workspace(1000, 1, 16, 10)
     assert L.cgv2_bin_sort(ctypes.byref(p), ctypes.byref(cam), 1, 10, ctypes.byref(bins), ctypes.c_void_p(256),
                            need - 1, None) == _lib.CGV2_EWORKSPACE
     v = ctypes.c_void_p(256)

@@ -1,0 +1,157 @@
+"""Parity at the benchmark's full size: 1 M surfels on the aerial city, 1600x1066, launched exactly as
+bench.py launches it (one view per call).  Lists are compared in full (bit-exact); images on sampled
+tiles the oracle renders one by one; gradients with the upstream restricted to the sampled tiles, so
+the oracle's reverse pass covers exactly what the GPU's does; loss and densify in full."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_00771_amd import scenes
+from tests.helpers import FRAGILE, IMG_TOL, fetch_bins, fetch_proj, grad_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def aerial(cuda):
+    import torch
+    from paper_2411_00771_amd import raster
+    w = scenes.workload(1)
+    sc = w["scene"]
+    params = raster.Params.from_scene(sc)
+    out = []
+    for vi in (0, 3):  # the sparsest and the densest of the 16 views
+        cam = w["cameras"][vi]
+        eng = raster.Engine(sc.n, cam.width, cam.height, 1, capacity=4_000_000)
+        cs = eng.cams([cam])
+        eng.status.zero_()
+        eng.forward(params, cs)
+        torch.cuda.synchronize()
+        assert eng.status.item() == 0
+        out.append(dict(cam=cam, eng=eng, cs=cs))
+    return dict(sc=sc, params=params, views=out)
+
+
+def _sample_tiles(eng, ranges, k=48, seed=0):
+    rng = np.random.default_rng(seed)
+    lens = np.diff(ranges)
+    longest = np.argsort(lens)[-8:]
+    pick = rng.choice(len(lens), size=k, replace=False)
+    return np.unique(np.concatenate([pick, longest])).astype(np.int32)
+
+
+@pytest.mark.parametrize("view", [0, 1])
+def test_aerial_bins_bit_exact_and_images_on_sampled_tiles(aerial, view):
+    v = aerial["views"][view]
+    eng, cam = v["eng"], v["cam"]
+    P = fetch_proj(eng)
+    ranges, ids = fetch_bins(eng)
+    o_off, o_ids = oracle.bin_tiles(P["rect"][0], P["rec"][0, :, 11].astype(np.float32), cam.width, cam.height)
+    assert np.array_equal(ranges, o_off) and np.array_equal(ids, o_ids)
+    po = oracle.project(aerial["sc"], cam)
+    vis = (po["flags"] & 1) > 0
+    assert np.mean(vis != ((P["flags"][0] & 1) > 0)) < 1e-5
+    both = vis & ((P["flags"][0] & 1) > 0)
+    # depth keys: both sides round an FP64 depth to FP32 once, so the keys agree bit for bit
+    kg = P["rec"][0, both, 11].astype(np.float32).view(np.uint32)
+    ko = po["depth32"][both].view(np.uint32)
+    assert np.count_nonzero(kg != ko) <= max(2, int(1e-6 * both.sum()))
+    M = po["M"][both]
+    cx = P["rec"][0, both, 0].astype(np.float64) + P["rec"][0, both, 2]
+    assert np.abs(cx - M[:, 2] / M[:, 8]).max() < 2e-5
+    off, oids = oracle.bin_tiles(po["tile_rect"], po["depth32"], cam.width, cam.height)
+    tiles = _sample_tiles(eng, ranges)
+    ref, ne, nc = oracle.render_tiles(po, cam, off, oids, tiles)
+    tx = eng.tiles_x
+    rgb = eng.rgb[0].cpu().numpy()
+    alpha = eng.alpha[0].cpu().numpy()
+    dmed = eng.depth_med[0].cpu().numpy()
+    worst, fragile, total = 0.0, 0, 0
+    for s, t in enumerate(tiles):
+        oy, ox = (t // tx) * 16, (t % tx) * 16
+        h, w = min(16, cam.height - oy), min(16, cam.width - ox)
+        r = ref[s, :h, :w]
+        ok = r[..., 10] >= FRAGILE
+        fragile += int((~ok).sum())
+        total += h * w
+        g_rgb = rgb[:, oy:oy + h, ox:ox + w].transpose(1, 2, 0)
+        worst = max(worst, float(np.abs(g_rgb - r[..., 0:3])[ok].max(initial=0)))
+        worst = max(worst, float(np.abs(alpha[oy:oy + h, ox:ox + w] - r[..., 8])[ok].max(initial=0)))
+        zs = max(1.0, float(np.abs(r[..., 4]).max()))
+        worst = max(worst, float(np.abs(dmed[oy:oy + h, ox:ox + w] - r[..., 4])[ok].max(initial=0)) / zs)
+    assert fragile <= 5e-3 * total, (fragile, total)
+    assert worst <= IMG_TOL, worst
+
+
+def test_aerial_loss_full_size(aerial, cuda):
+    import torch
+    v = aerial["views"][1]
+    eng, cam = v["eng"], v["cam"]
+    tgt = scenes.random_target(5, cam.width, cam.height)
+    lv = eng.loss(torch.from_numpy(tgt).to(cuda)[None])
+    torch.cuda.synchronize()
+    img = eng.rgb[0].cpu().numpy().astype(np.float64)
+    ref = oracle.ssim_loss(img, tgt)
+    assert abs(lv[0, 0].item() - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    dt = eng.d_img[0].cpu().numpy()
+    assert np.abs(dt - ref["d_total"]).max() <= 1e-4 * np.abs(ref["d_total"]).max()
+    ds = eng.d_img_ssim[0].cpu().numpy()
+    assert np.abs(ds - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
+
+
+def test_aerial_backward_on_sampled_tiles_and_densify(aerial, cuda):
+    import torch
+    from paper_2411_00771_amd import raster
+    v = aerial["views"][1]
+    eng, cam, cs = v["eng"], v["cam"], v["cs"]
+    sc, params = aerial["sc"], aerial["params"]
+    ranges, _ = fetch_bins(eng)
+    tiles = _sample_tiles(eng, ranges, k=32, seed=1)
+    H, W = cam.height, cam.width
+    mask_px = np.zeros((H, W), bool)
+    tx = eng.tiles_x
+    for t in tiles:
+        oy, ox = (t // tx) * 16, (t % tx) * 16
+        mask_px[oy:oy + 16, ox:ox + 16] = True
+    po = oracle.project(sc, cam)
+    off, oids = oracle.bin_tiles(po["tile_rect"], po["depth32"], W, H)
+    ref_tiles, _, _ = oracle.render_tiles(po, cam, off, oids, tiles)
+    # exclude pixels whose decisions are fragile
+    for s, t in enumerate(tiles):
+        oy, ox = (t // tx) * 16, (t % tx) * 16
+        h, w = min(16, H - oy), min(16, W - ox)
+        mask_px[oy:oy + h, ox:ox + w] &= ref_tiles[s, :h, :w, 10] >= FRAGILE
+    rng = np.random.default_rng(9)
+    up = dict(d_rgb=rng.normal(size=(3, H, W)) * 1e-6, d_rgb_ssim=rng.normal(size=(3, H, W)) * 1e-6,
+              d_depth=rng.normal(size=(H, W)) * 1e-9, d_normal=rng.normal(size=(3, H, W)) * 1e-7,
+              d_alpha=rng.normal(size=(H, W)) * 1e-7)
+    up = {k: (a * mask_px).astype(np.float32) for k, a in up.items()}
+    eng.forward(params, cs)
+    g = raster.Grads(params, 1)
+    eng.backward(params, cs, g, **{k: torch.from_numpy(a).to(cuda)[None].contiguous() for k, a in up.items()})
+    st = raster.DensifyState(sc.n)
+    eng.densify(params, g, st)
+    torch.cuda.synchronize()
+    tmask = np.zeros(len(off) - 1, np.uint8)
+    tmask[tiles] = 1
+    up64 = {k: a.astype(np.float64) for k, a in up.items()}
+    og = oracle.render_bwd(po, cam, off, oids, d_rgb=up64["d_rgb"], d_depth=up64["d_depth"],
+                           d_normal=up64["d_normal"], d_alpha=up64["d_alpha"], tile_mask=tmask)
+    pg = oracle.project_bwd(sc, cam, og)
+    for name in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
+        grad_close(name, getattr(g, name).cpu().numpy(), pg[name])
+    gt = oracle.viewspace_grad(po["M"], og["M"], W, H)
+    grad_close("g_view_total", g.g_view_total[0].cpu().numpy().T, gt)
+    os_ = oracle.render_bwd(po, cam, off, oids, d_rgb=up64["d_rgb_ssim"], tile_mask=tmask)
+    grad_close("g_view_ssim", g.g_view_ssim[0].cpu().numpy().T, oracle.viewspace_grad(po["M"], os_["M"], W, H))
+    # densify on the GPU's own view-space gradients (full size, 1 M surfels)
+    P = fetch_proj(eng)
+    ost = oracle.new_densify_state(sc.n)
+    r = oracle.densify_stats(g.g_view_total[0].cpu().numpy().T.astype(np.float64),
+                             g.g_view_ssim[0].cpu().numpy().T.astype(np.float64), (P["flags"][0] & 1) > 0,
+                             P["radius"][0], sc.log_scale, ost)
+    assert abs(st.scale[0].item() / r["scale"] - 1) <= 1e-6
+    assert np.allclose(st.accum_dgd.cpu().numpy(), ost["accum_dgd"], rtol=1e-5, atol=1e-20)
+    assert np.array_equal(st.denom.cpu().numpy(), ost["denom"])
+    assert int(st.counters[0].item()) == int(r["counters"][0])
+    assert int(st.counters[2].item()) == int(r["counters"][2])

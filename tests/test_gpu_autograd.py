@@ -1,0 +1,101 @@
+"""Differentiation form: Rasterize2DGS / L1SSIMLoss as torch.autograd Functions.
+
+A 512-surfel crop of the aerial generator (the surfels nearest a ground point) in a 64x64 window:
+autograd gradients vs the oracle's analytic gradients and vs FP64 central differences (eps 1e-4) of
+the oracle's loss; an 8-view launch equals the sum of single-view launches; nothing per fragment is
+saved for the backward."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_00771_amd import scenes
+from tests.helpers import FRAGILE, grad_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _crop_and_cams(n_views=8):
+    city = scenes.make_city(2, L=400.0, n_boxes=10)
+    sc_full = scenes.city_scene(2, 60_000, L=400.0, city=city)
+    c0 = np.array([10.0, -20.0, float(city.height(np.array([10.0]), np.array([-20.0]))[0])])
+    d = np.linalg.norm(sc_full.mean.T.astype(np.float64) - c0, axis=1)
+    sc = sc_full.subset(np.sort(np.argsort(d)[:512]))
+    cams = []
+    rng = np.random.default_rng(3)
+    for k in range(n_views):
+        off = rng.normal(size=2) * 3.0
+        pos = c0 + np.array([off[0], off[1], 25.0 + 3 * k])
+        fwd = c0 - pos
+        cams.append(scenes._look_camera(pos, fwd, np.array([1.0, 0.0, 0.0]), 64, 64, 50.0))
+    return sc, cams
+
+
+def _autograd_grads(sc, cams, targets, cuda):
+    import torch
+    from paper_2411_00771_amd import raster
+    eng = raster.Engine(sc.n, 64, 64, len(cams), capacity=1 << 18)
+    cs = eng.cams(cams)
+    ts = [torch.from_numpy(getattr(sc, k)).to(cuda).requires_grad_(True)
+          for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")]
+    rgb, depth, dmed, normal, alpha = raster.rasterize(ts, eng, cs, sc.sh_degree)
+    loss = raster.L1SSIMLoss.apply(rgb, torch.from_numpy(np.stack(targets)).to(cuda), eng, 0.2)
+    loss.backward()
+    torch.cuda.synchronize()
+    assert eng.status.item() == 0
+    return eng, [t.grad.cpu().numpy() for t in ts], loss.item()
+
+
+def test_autograd_matches_oracle_and_fd(cuda):
+    sc, cams = _crop_and_cams(1)
+    cam = cams[0]
+    tgt = scenes.random_target(7, 64, 64)
+    eng, g, lval = _autograd_grads(sc, [cam], [tgt], cuda)
+    # oracle analytic gradient on the same loss
+    P = oracle._scene64(sc)
+    proj, off, ids, img = oracle.forward_view(P, cam)
+    assert (img["margin"] < FRAGILE).mean() <= 5e-3
+    lo = oracle.ssim_loss(img["rgb"], tgt)
+    assert abs(lval - lo["loss"]) <= 1e-5 * lo["loss"]
+    ref = oracle.backward_view(P, cam, proj, off, ids, dict(d_rgb=lo["d_total"]))["params"]
+    names = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+    for name, gg in zip(names, g):
+        grad_close(name, gg, ref[name])
+    # FP64 central differences of the oracle loss on sampled parameters, eps = 1e-4
+    rng = np.random.default_rng(0)
+    eps = 1e-4
+    sig0 = img["sig"]
+    for name, gg in zip(names, g):
+        flat = P[name].reshape(-1)
+        fd, an = [], []
+        for i in rng.choice(flat.size, 12, replace=False):
+            vals = []
+            for sgn in (1, -1):
+                Q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in P.items()}
+                Q[name].reshape(-1)[i] += sgn * eps
+                _, _, _, im2 = oracle.forward_view(Q, cam)
+                vals.append((oracle.ssim_loss(im2["rgb"], tgt)["loss"], im2["sig"]))
+            if not (np.array_equal(vals[0][1], sig0) and np.array_equal(vals[1][1], sig0)):
+                continue
+            fd.append((vals[0][0] - vals[1][0]) / (2 * eps))
+            an.append(gg.reshape(-1)[i])
+        fd, an = np.array(fd), np.array(an)
+        if len(fd) >= 4:
+            assert np.linalg.norm(fd - an) <= 2e-3 * np.linalg.norm(fd) + 1e-9, name
+
+
+def test_batched_views_equal_sum_of_single_views(cuda):
+    sc, cams = _crop_and_cams(8)
+    tg = [scenes.random_target(20 + k, 64, 64) for k in range(8)]
+    eng8, g8, l8 = _autograd_grads(sc, cams, tg, cuda)
+    acc = [np.zeros_like(x) for x in g8]
+    ltot = 0.0
+    for k in range(8):
+        _, g1, l1 = _autograd_grads(sc, [cams[k]], [tg[k]], cuda)
+        for a, b in zip(acc, g1):
+            a += b
+        ltot += l1
+    assert abs(l8 - ltot) <= 1e-5 * abs(ltot)
+    for name, a, b in zip(("mean", "log_scale", "quat", "opacity_logit", "sh"), g8, acc):
+        grad_close(name, a, b, rel=1e-4)
+    # the only state kept for the backward is the per-pixel checkpoint (12 B / pixel) + bins
+    assert eng8.T_final.element_size() * eng8.T_final.numel() == 4 * 8 * 64 * 64

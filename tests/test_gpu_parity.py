@@ -39,7 +39,7 @@ def test_project_matches_oracle(tiny):
     assert np.abs(rec[v, 13:16] - po["rgb"][v]).max() <= 2e-6
     assert np.abs(rec[v, 16:19] - po["normal"][v]).max() <= 1e-6
     assert np.abs(rec[v, 12] - po["opacity"][v]).max() <= 1e-6
-    assert np.abs(rec[v, 11] / po["depth"][v] - 1).max() <= 1e-6
+    assert np.array_equal(rec[v, 11].astype(np.float32).view(np.uint32), po["depth32"][v].view(np.uint32))
     M = po["M"][v]
     cx = rec[v, 0].astype(np.float64) + rec[v, 2]
     cy = rec[v, 1].astype(np.float64) + rec[v, 3]
