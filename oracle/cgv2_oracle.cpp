@@ -229,11 +229,28 @@ void geometry(const Params& P, const Cam& cam, int64_t i, Geo& g) {
   for (int r = 0; r < 3; ++r) g.dir[r] = v[r] / g.dist;
 }
 
+// Fragility margins only (never results): an FP32 evaluation of the intersection is modelled as
+// exact arithmetic on data carrying a relative error of kU32 -- every coefficient of the affine map
+// (x', y') -> p written in the frame centred on the projected centre, and the offsets x', y' themselves
+// (rounded relative to a tile origin at most 16 px away) -- propagated to first order through
+// u = p0/p2, v = p1/p2 and rho, times a safety factor.  (Emulating the FP32 evaluation of 1.6e5
+// (pixel, surfel) pairs of a 10 M-surfel aerial view gave actual / bound <= 1.32 before the factor.)
+// T carries the relative errors of its alpha factors and two roundings per step.
+const double kU32 = 5.9604644775390625e-8;  // 2^-24
+const double kErrSafety = 3.0;
+
 // ray-splat evaluation at pixel sample (x, y) for a screen transform M (row-major)
 struct Eval {
   double a[3], b[3], p[3], rho3, rho2, rho, G, araw, alpha, zf, u, v, cxp, cyp;
+  double drho3, drho2, dalpha_rel;  // error bounds of rho3, rho2 and relative bound of alpha (FP32 model)
   bool is3d, clamped;
 };
+
+inline void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
 
 void evaluate(const double* M, double o, double x, double y, Eval& e) {
   const double* m1 = M;
@@ -262,6 +279,29 @@ void evaluate(const double* M, double o, double x, double y, Eval& e) {
   e.clamped = e.araw > kAlphaMax;
   e.alpha = e.clamped ? kAlphaMax : e.araw;
   e.zf = e.is3d ? (m3[0] * e.u + m3[1] * e.v + m3[2]) : M[8];
+
+  // error model (see kU32): with a = dx m3 + a0, b = dy m3 + b0 (a0 = cx m3 - m1, b0 = cy m3 - m2),
+  // p = dx (m3 x b0) + dy (a0 x m3) + a0 x b0
+  const double eps = kErrSafety * kU32;
+  double a0[3], b0[3], px[3], py[3], p0[3];
+  for (int k = 0; k < 3; ++k) { a0[k] = e.cxp * m3[k] - m1[k]; b0[k] = e.cyp * m3[k] - m2[k]; }
+  cross3(m3, b0, px);
+  cross3(a0, m3, py);
+  cross3(a0, b0, p0);
+  const double ax = std::fabs(dx), ay = std::fabs(dy);
+  double dp[3];
+  for (int k = 0; k < 3; ++k)
+    dp[k] = eps * (std::fabs(p0[k]) + (2 * ax + kTile) * std::fabs(px[k]) + (2 * ay + kTile) * std::fabs(py[k]));
+  if (std::isfinite(e.rho3)) {
+    const double ap2 = std::fabs(e.p[2]);
+    const double du = (dp[0] + std::fabs(e.u) * dp[2]) / ap2, dv = (dp[1] + std::fabs(e.v) * dp[2]) / ap2;
+    e.drho3 = 2 * (std::fabs(e.u) * du + std::fabs(e.v) * dv) + eps * e.rho3;
+  } else {
+    e.drho3 = INFINITY;
+  }
+  e.drho2 = eps * (e.rho2 + 2 * (ax * (ax + kTile) + ay * (ay + kTile)) / kSigmaF2);
+  // alpha = o exp(-rho/2): relative error rho's half plus the rounding of log2(o) and exp2
+  e.dalpha_rel = 0.5 * (e.is3d ? e.drho3 : e.drho2) + eps * (2 + std::fabs(std::log2(o)));
 }
 
 uint32_t f32bits(double z) {
@@ -271,7 +311,9 @@ uint32_t f32bits(double z) {
   return b;
 }
 
-inline double relmargin(double v, double thr) { return std::fabs(v - thr) / std::fabs(thr); }
+// relative distance of a positive quantity to a threshold, in log space (|ln(v / thr)|, which is the
+// relative difference near the threshold and compares directly with a relative error bound)
+inline double relmargin(double v, double thr) { return v > 0 ? std::fabs(std::log(v / thr)) : INFINITY; }
 
 struct PixOut {
   double C[3], D, Dmed, N[3], A, T;
@@ -288,22 +330,29 @@ void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const 
   double T = 1, C[3] = {0, 0, 0}, D = 0, N[3] = {0, 0, 0}, Dmed = 0;
   int64_t med = -1, last = start, n_eval = 0, n_con = 0;
   double margin = INFINITY;
+  double dT = 0;  // relative error bound of T under the FP32 error model
   uint64_t sig = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
   Eval e;
+  // each margin is a relative distance to a decision threshold, net of the FP32 error bound of the
+  // quantity decided on
   for (int64_t k = start; k < end; ++k) {
     const int64_t n = id_of(k);
     ++n_eval;
     evaluate(M + 9 * n, opac[n], x, y, e);
-    margin = std::min(margin, relmargin(e.alpha, kAlphaMin));
+    margin = std::min(margin, relmargin(e.alpha, kAlphaMin) - e.dalpha_rel);
     if (e.alpha < kAlphaMin) continue;
     const double Tn = T * (1 - e.alpha);
-    margin = std::min(margin, 0.1 * relmargin(Tn, kTmin));
+    const double dTn =
+        dT + (e.clamped ? 0.0 : e.alpha / (1 - e.alpha) * e.dalpha_rel) + 2 * kErrSafety * kU32;
+    margin = std::min(margin, relmargin(Tn, kTmin) - dTn);
     if (Tn < kTmin) { mix(0xffffffffull); break; }
     ++n_con;
-    margin = std::min(margin, relmargin(e.araw, kAlphaMax));
-    if (std::isfinite(e.rho3)) margin = std::min(margin, std::fabs(e.rho3 - e.rho2) / std::max(e.rho3, e.rho2));
-    margin = std::min(margin, 0.1 * relmargin(T, 0.5));
+    margin = std::min(margin, relmargin(e.araw, kAlphaMax) - e.dalpha_rel);
+    if (std::isfinite(e.rho3))
+      margin = std::min(margin, (std::fabs(e.rho3 - e.rho2) - e.drho3 - e.drho2) / std::max(e.rho3, e.rho2));
+    margin = std::min(margin, relmargin(T, 0.5) - dT);
+    dT = dTn;
     mix((uint64_t)n * 4 + (e.is3d ? 1 : 0) + (e.clamped ? 2 : 0));
     const double w = e.alpha * T;
     for (int c = 0; c < 3; ++c) { C[c] += w * rgb[3 * n + c]; N[c] += w * nrm[3 * n + c]; }
