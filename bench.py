@@ -148,7 +148,8 @@ def bench_serving(seconds, warmup_s, slots, n=None):
     arrivals = [t for t, _ in reqs]
     out = {}
     for name, ns in (("continuous", slots), ("plain_queue", 1)):
-        srv = server.Server(params, max_slots=ns, arena_bytes=32 << 30, intersections_per_pixel=3.0)
+        srv = server.Server(params, max_slots=ns, arena_bytes=32 << 30, intersections_per_pixel=3.0,
+                            keep_results=False)
         # warm the allocator and the kernels
         for c in cams[:8]:
             srv.render_alone(c)
@@ -185,6 +186,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this rasterizer build has no multi-GPU path "
@@ -194,6 +197,12 @@ def main():
     import torch
     from paper_2411_00771_amd import raster, scenes
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     w = scenes.workload(1, n_override=args.n)
     sc, cams_all = w["scene"], w["cameras"]

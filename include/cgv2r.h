@@ -42,7 +42,7 @@ extern "C" {
 #define CGV2_EHIP (-4)        /* a HIP launch failed */
 
 #define CGV2_TILE 16
-#define CGV2_REC_FLOATS 20    /* floats per render record, see cgv2_proj */
+#define CGV2_REC_FLOATS 24    /* floats per render record, see cgv2_proj */
 
 /* project flags (cgv2_proj.flags) */
 #define CGV2_F_VISIBLE 1u     /* tile rect non-empty: the surfel is binned in this view */
@@ -73,7 +73,7 @@ typedef struct {
   const float *mean, *log_scale, *quat, *opacity_logit, *sh;
 } cgv2_surfels;
 
-/* Per-view projection.  rec[V][n][20] is written for visible surfels only:
+/* Per-view projection.  rec[V][n][24] is written for visible surfels only:
  *   0,1  cx_hi, cy_hi   integer part of the projected centre (pixels)
  *   2,3  cx_lo, cy_lo   remainder: centre = hi + lo
  *   4-7  a11 a12 a21 a22  with x' = x - cx, y' = y - cy the ray through (x, y) meets the surfel
@@ -81,6 +81,8 @@ typedef struct {
  *                        w = w0 + w1 x' + w2 y' (the inverse homography, scaled to max |coef| = 1)
  *   11   z_c            centre depth (sort key); intersection depth = z_c w0 / w
  *   12   opacity        13-15 rgb   16-18 camera-space normal (facing the camera)   19 k^2 cutoff
+ *   20,21 pixel rect (i0 | i1 << 16), (j0 | j1 << 16) as uint32 bits (inclusive, clamped to the image)
+ *   22,23 zero
  * rect[V][n][4] = tx0, ty0, tx1, ty1 (end exclusive; all 0 when not visible); radius[V][n] screen
  * radius in pixels; flags[V][n] CGV2_F_* bits (written for every surfel).
  * visible[V * n], visible_start[V + 1]: written by cgv2_bin_sort; entries visible[visible_start[v] ..

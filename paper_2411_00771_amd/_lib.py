@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libcgv2r.so")
 
 CGV2_OK, CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EUNSUPPORTED, CGV2_EHIP = 0, -1, -2, -3, -4
 TILE = 16
-REC_FLOATS = 20
+REC_FLOATS = 24
 F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["cgv2_project", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",

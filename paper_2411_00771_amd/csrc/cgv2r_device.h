@@ -14,7 +14,7 @@ constexpr int kGradFields = 19;  // per-surfel, per-view record gradients accumu
 // record field offsets
 enum : int {
   R_CXH = 0, R_CYH, R_CXL, R_CYL, R_A11, R_A12, R_A21, R_A22, R_W0, R_W1, R_W2,
-  R_ZC, R_OP, R_R, R_G, R_B, R_NX, R_NY, R_NZ, R_K2
+  R_ZC, R_OP, R_R, R_G, R_B, R_NX, R_NY, R_NZ, R_K2, R_PXR, R_PYR
 };
 
 // record-gradient field offsets ([V][kGradFields][n] in the backward workspace); the first 16 are the

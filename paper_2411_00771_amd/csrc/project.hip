@@ -284,6 +284,8 @@ __device__ __forceinline__ bool project_one(const cgv2_surfels& s, const DevCam&
   rp[2] = make_float4((float)(h.W[0] * sc), (float)(h.W[1] * sc), (float)(h.W[2] * sc), (float)M[8]);
   rp[3] = make_float4((float)g.o, col[0], col[1], col[2]);
   rp[4] = make_float4(g.nc[0], g.nc[1], g.nc[2], (float)k2);
+  const uint32_t pxr = (uint32_t)i0 | ((uint32_t)i1 << 16), pyr = (uint32_t)j0 | ((uint32_t)j1 << 16);
+  rp[5] = make_float4(__uint_as_float(pxr), __uint_as_float(pyr), 0.f, 0.f);
   return true;
 }
 

@@ -204,6 +204,8 @@ class Engine:
 
     def backward(self, params: Params, cams, grads: Grads, d_rgb=None, d_depth=None, d_depth_med=None,
                  d_normal=None, d_alpha=None, d_rgb_ssim=None):
+        if grads.g_view_total.shape[0] < self.V:
+            raise ValueError("gradients hold fewer views than the engine")
         up = _lib.ImageGrad(ptr(d_rgb), ptr(d_depth), ptr(d_depth_med), ptr(d_normal), ptr(d_alpha),
                             ptr(d_rgb_ssim))
         check(_lib.lib().cgv2_render_bwd(ctypes.byref(params.struct()), ctypes.byref(self._proj),
@@ -213,6 +215,10 @@ class Engine:
 
     def densify(self, params: Params, grads: Grads, state: DensifyState, omega=0.9, eta_min=0.05,
                 grad_threshold=2e-4):
+        if state.scale.numel() < self.V or state.mask.numel() < self.n:
+            raise ValueError("densify state holds fewer views or surfels than the engine")
+        if grads.g_view_total.shape[0] < self.V:
+            raise ValueError("gradients hold fewer views than the engine")
         prm = _lib.DensifyParams(omega, eta_min, grad_threshold)
         check(_lib.lib().cgv2_densify_stats(ctypes.byref(params.struct()), ctypes.byref(self._proj),
                                             ctypes.byref(grads.struct()), self.V, ctypes.byref(prm),

@@ -61,8 +61,10 @@ class _Slot:
 class Server:
     def __init__(self, params: raster.Params, max_slots: int = 4, arena_bytes: int = 8 << 30,
                  max_width: int = 3840, max_height: int = 2160, intersections_per_pixel: float = 2.0,
-                 device="cuda"):
+                 keep_results: bool = True, device="cuda"):
         self.params = params
+        # False: a finished request's images are released at once (load generators that only time)
+        self.keep_results = keep_results
         self.n = params.n
         self.max_w, self.max_h = max_width, max_height
         self.arena_bytes = int(arena_bytes)
@@ -128,6 +130,8 @@ class Server:
                 self.queue.appendleft(r)
                 continue
             r.done_t = now
+            if not self.keep_results:
+                r.result = None
             self.finished.append(r)
         for slot in self.slots:
             if slot.req is not None or not self.queue:

@@ -23,7 +23,7 @@ def gpu_forward(scene, cams, capacity=None, target=None):
 
 def fetch_proj(eng):
     V, n = eng.V, eng.n
-    rec = eng.rec.view(V, n, 20).cpu().numpy()
+    rec = eng.rec.view(V, n, 24).cpu().numpy()
     rect = eng.rect.view(V, n, 4).cpu().numpy().view(np.uint16).astype(np.int32)
     return dict(rec=rec, rect=rect, radius=eng.radius.view(V, n).cpu().numpy(),
                 flags=eng.flags.view(V, n).cpu().numpy().astype(np.int32))
