@@ -208,6 +208,23 @@ int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bin
                     int32_t V, const cgv2_image* img, const cgv2_image_grad* up, cgv2_grads* grads,
                     void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* The two stages of cgv2_render_bwd, callable on their own (same stream order, same workspace):
+ *
+ * cgv2_render_bwd_records: the reverse traversal of Eq. 1 only.  Writes, into the workspace, the
+ * gradients of each (view, visible surfel) render record: the 9 screen-transform terms, opacity, colour,
+ * the SSIM-only screen-position pair, the intersection depth and the normal (unspecified layout; the
+ * workspace must stay untouched until cgv2_project_bwd has read it).
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP.
+ *
+ * cgv2_project_bwd: chains those record gradients to the parameters (d_* of grads, added to) and writes
+ * both view-space gradients of every view.  proj, cams and V must be those of the records call.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_render_bwd_records(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V,
+                            int64_t n, const cgv2_image* img, const cgv2_image_grad* up, void* workspace,
+                            size_t ws_bytes, void* hip_stream);
+int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_camera* cams, int32_t V,
+                     const void* workspace, size_t ws_bytes, cgv2_grads* grads, void* hip_stream);
+
 /* Workspace bytes for cgv2_densify_stats. */
 size_t cgv2_densify_workspace(int64_t n, int32_t V);
 

@@ -17,7 +17,8 @@ REC_FLOATS = 24
 F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["cgv2_project", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
-           "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_densify_workspace",
+           "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
+           "cgv2_project_bwd", "cgv2_densify_workspace",
            "cgv2_densify_stats", "cgv2_render_count", "cgv2_strerror", "cgv2_last_hip_error"]
 
 P = ctypes.c_void_p
@@ -97,6 +98,11 @@ def lib():
         "cgv2_render_bwd": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Bins),
                                            ctypes.POINTER(Camera), i32, ctypes.POINTER(Image),
                                            ctypes.POINTER(ImageGrad), ctypes.POINTER(Grads), P, sz, P]),
+        "cgv2_render_bwd_records": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Bins), ctypes.POINTER(Camera),
+                                                   i32, i64, ctypes.POINTER(Image), ctypes.POINTER(ImageGrad), P, sz,
+                                                   P]),
+        "cgv2_project_bwd": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Camera), i32,
+                                            P, sz, ctypes.POINTER(Grads), P]),
         "cgv2_densify_workspace": (sz, [i64, i32]),
         "cgv2_densify_stats": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Grads), i32,
                                               ctypes.POINTER(DensifyParams), ctypes.POINTER(DensifyState), P, sz, P]),

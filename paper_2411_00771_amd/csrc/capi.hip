@@ -61,6 +61,49 @@ cgv2::CamPack pack(const cgv2_camera* c, int v0, int count) {
 inline int tiles_x(const cgv2_camera* c) { return (c[0].width + CGV2_TILE - 1) / CGV2_TILE; }
 inline int tiles_y(const cgv2_camera* c) { return (c[0].height + CGV2_TILE - 1) / CGV2_TILE; }
 
+cgv2::RecGrads rec_grads(void* workspace, int64_t n, int32_t V) {
+  cgv2::RecGrads rg;
+  rg.row = (float*)workspace;
+  rg.nrm = rg.row + (size_t)cgv2::kGradRow * (size_t)n * (size_t)V;
+  return rg;
+}
+
+int bwd_records(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                const cgv2_image* img, const cgv2_image_grad* up, void* workspace, hipStream_t st) {
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  const cgv2::RecGrads rg = rec_grads(workspace, n, V);
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_render_bwd(*proj, *bins, pack(cams, v0, cnt), n, tx, ty, *img, *up, rg, st));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+int bwd_project(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_camera* cams, int32_t V,
+                const void* workspace, cgv2_grads* g, hipStream_t st) {
+  const cgv2::RecGrads rg = rec_grads(const_cast<void*>(workspace), s->n, V);
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_project_bwd(*s, pack(cams, v0, cnt), *proj, rg, *g, st));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
+bool records_args_ok(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                     const cgv2_image* img, const cgv2_image_grad* up) {
+  return proj_ok(proj) && bins_ok(bins) && cams_ok(cams, V) && img && up && n >= 0 && img->T_final && img->last &&
+         img->med;
+}
+
+bool project_args_ok(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_camera* cams, int32_t V,
+                     const cgv2_grads* g) {
+  if (!surfels_ok(s) || !proj_ok(proj) || !cams_ok(cams, V) || !g) return false;
+  return s->n == 0 || (g->d_mean && g->d_log_scale && g->d_quat && g->d_opacity_logit && g->d_sh);
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -149,28 +192,32 @@ int cgv2_loss(const float* img, const float* target, int32_t V, int32_t width, i
 
 size_t cgv2_render_bwd_workspace(int64_t n, int32_t V) {
   if (n < 0 || V < 1) return 0;
-  return ((size_t)cgv2::kGradFields * sizeof(float) * (size_t)n * (size_t)V + 255) & ~(size_t)255;
+  return ((size_t)(cgv2::kGradRow + cgv2::kGradNrm) * sizeof(float) * (size_t)n * (size_t)V + 255) & ~(size_t)255;
 }
 
 int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams,
                     int32_t V, const cgv2_image* img, const cgv2_image_grad* up, cgv2_grads* g, void* workspace,
                     size_t ws_bytes, void* stream) {
-  if (!surfels_ok(s) || !proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !img || !up || !g) return CGV2_EINVAL;
-  if (!img->T_final || !img->last || !img->med) return CGV2_EINVAL;
-  if (s->n > 0 && (!g->d_mean || !g->d_log_scale || !g->d_quat || !g->d_opacity_logit || !g->d_sh))
+  if (!project_args_ok(s, proj, cams, V, g) || !records_args_ok(proj, bins, cams, V, s->n, img, up))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_render_bwd_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
-  const int tx = tiles_x(cams), ty = tiles_y(cams);
-  float* rg = (float*)workspace;
-  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
-    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
-    int rc = hip_status(cgv2_launch_render_bwd(*proj, *bins, pack(cams, v0, cnt), s->n, tx, ty, *img, *up, rg,
-                                               (hipStream_t)stream));
-    if (rc) return rc;
-    rc = hip_status(cgv2_launch_project_bwd(*s, pack(cams, v0, cnt), *proj, rg, *g, (hipStream_t)stream));
-    if (rc) return rc;
-  }
-  return CGV2_OK;
+  const int rc = bwd_records(proj, bins, cams, V, s->n, img, up, workspace, (hipStream_t)stream);
+  return rc ? rc : bwd_project(s, proj, cams, V, workspace, g, (hipStream_t)stream);
+}
+
+int cgv2_render_bwd_records(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V,
+                            int64_t n, const cgv2_image* img, const cgv2_image_grad* up, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!records_args_ok(proj, bins, cams, V, n, img, up)) return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_render_bwd_workspace(n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return bwd_records(proj, bins, cams, V, n, img, up, workspace, (hipStream_t)stream);
+}
+
+int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_camera* cams, int32_t V,
+                     const void* workspace, size_t ws_bytes, cgv2_grads* g, void* stream) {
+  if (!project_args_ok(s, proj, cams, V, g)) return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_render_bwd_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return bwd_project(s, proj, cams, V, workspace, g, (hipStream_t)stream);
 }
 
 size_t cgv2_densify_workspace(int64_t n, int32_t V) {

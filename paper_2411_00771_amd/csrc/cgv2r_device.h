@@ -17,11 +17,21 @@ enum : int {
   R_ZC, R_OP, R_R, R_G, R_B, R_NX, R_NY, R_NZ, R_K2, R_PXR, R_PYR
 };
 
-// record-gradient field offsets ([V][kGradFields][n] in the backward workspace); the first 16 are the
-// slots of the wave reduce-scatter in the reverse pass
+// record-gradient fields accumulated by the reverse pass; the first 16 are the slots of its wave
+// reduce-scatter
 enum : int {
   G_CX = 0, G_CY, G_A11, G_A12, G_A21, G_A22, G_W0, G_W1, G_W2, G_OP, G_R, G_G, G_B, G_SCX, G_SCY, G_ZC,
   G_NX, G_NY, G_NZ
+};
+
+// Record gradients in the backward workspace.  Fields G_CX..G_ZC of (view v, surfel i) form one 64-B
+// row row[(v n + i) 16 + f], so the 16 atomics a wave issues for a (surfel, tile) fall in one cache
+// line; the normal fields follow all views' rows as 16-B rows nrm[(v n + i) 4 + c] (c < 3).
+constexpr int kGradRow = 16;
+constexpr int kGradNrm = 4;
+struct RecGrads {
+  float* row;
+  float* nrm;
 };
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
@@ -107,14 +117,18 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
   if (i < count) p[i] = v;
 }
 
-// Block -> tile mapping that keeps neighbouring tiles on one XCD: hardware dispatches
-// workgroup b to XCD b % 8, so XCD x receives the contiguous run [x*q, (x+1)*q).
+// Block -> tile mapping.  Hardware dispatches workgroup b to XCD b % 8.  Here XCD x receives the
+// runs of kXcdChunk consecutive tiles with run index = x (mod 8): neighbouring tiles of a run share
+// that XCD's L2, while the runs of every XCD are spread over the whole image.  (Giving each XCD one
+// contiguous band instead leaves the XCD with the densest band -- the far field of an oblique view --
+// with up to twice the mean work.)  Blocks past the last full round of 8 runs map to themselves.
+constexpr uint32_t kXcdChunk = 4;
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
-  const uint32_t q = nb / 8u, r = nb % 8u;
-  const uint32_t x = b % 8u, k = b / 8u;
-  // the first r XCDs take q + 1 blocks each
-  const uint32_t base = x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q;
-  return base + k;
+  const uint32_t span = 8u * kXcdChunk;
+  const uint32_t full = nb - nb % span;
+  if (b >= full) return b;
+  const uint32_t x = b % 8u, k = b / 8u;  // XCD and the block's rank on it
+  return (x + 8u * (k / kXcdChunk)) * kXcdChunk + k % kXcdChunk;
 }
 
 }  // namespace cgv2

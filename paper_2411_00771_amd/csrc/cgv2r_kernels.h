@@ -9,7 +9,7 @@
 
 hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st);
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
-                                   const float* rg, const cgv2_grads& g, hipStream_t st);
+                                   const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
@@ -21,7 +21,7 @@ hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, cons
                                     int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st);
 hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                   int tiles_x, int tiles_y, const cgv2_image& img, const cgv2_image_grad& up,
-                                  float* rg, hipStream_t st);
+                                  const cgv2::RecGrads& rg, hipStream_t st);
 
 size_t cgv2_loss_ws_layout(int W, int H, int V, size_t* off);
 hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, int H, float lambda, float* d_img,

@@ -306,7 +306,7 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cams,
                                                       const uint32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ vstart,
-                                                      const float* __restrict__ rg, cgv2_grads gr) {
+                                                      RecGrads rg, cgv2_grads gr) {
   const int64_t n = s.n;
   const uint32_t e0 = vstart[0], e1 = vstart[1];
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -318,9 +318,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
     const DevCam& c = cams.c[0];
     float* gvt = gr.g_view_total ? gr.g_view_total + (int64_t)v * 2 * n : nullptr;
     float* gvs = gr.g_view_ssim ? gr.g_view_ssim + (int64_t)v * 2 * n : nullptr;
-    const float* r = rg + (int64_t)v * kGradFields * n + i;
     float d[kGradFields];
-    for (int k = 0; k < kGradFields; ++k) d[k] = r[(int64_t)k * n];
+    {
+      const float4* r = (const float4*)(rg.row + ((int64_t)v * n + i) * kGradRow);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 q = r[k];
+        d[4 * k] = q.x; d[4 * k + 1] = q.y; d[4 * k + 2] = q.z; d[4 * k + 3] = q.w;
+      }
+      const float4 q = *(const float4*)(rg.nrm + ((int64_t)v * n + i) * kGradNrm);
+      d[G_NX] = q.x; d[G_NY] = q.y; d[G_NZ] = q.z;
+    }
     const float ndx = 0.5f * (float)c.W, ndy = 0.5f * (float)c.H;
     if (gvt) { gvt[i] = d[G_CX] * ndx; gvt[n + i] = d[G_CY] * ndy; }
     if (gvs) { gvs[i] = d[G_SCX] * ndx; gvs[n + i] = d[G_SCY] * ndy; }
@@ -438,7 +446,7 @@ hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams,
 }
 
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
-                                   const float* rg, const cgv2_grads& g, hipStream_t st) {
+                                   const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   const int64_t n = s.n;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);

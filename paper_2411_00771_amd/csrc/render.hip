@@ -283,7 +283,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 struct BwdArgs {
   RenderArgs r;
   cgv2_image_grad up;
-  float* rg;  // [V][kGradFields][n]
+  RecGrads rg;
 };
 
 __device__ __forceinline__ float ldg0(const float* p, int64_t i) { return p ? p[i] : 0.f; }
@@ -401,7 +401,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
   const int64_t vn = (int64_t)v * a.n;
   const int64_t HW = (int64_t)W * H;
-  float* rg = A.rg + (int64_t)v * kGradFields * a.n;
+  float* rgv = A.rg.row + (int64_t)v * a.n * kGradRow;
+  float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
 
   BwdState p[4];
 #pragma unroll
@@ -472,15 +473,16 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
       if ((lane & 12) == 0 && (kGeom || slot != G_ZC)) {
         // the staged numerator coefficients carry 1/sqrt(2)
         const bool anum = slot >= G_A11 && slot <= G_A22;
-        atomicAdd(rg + (int64_t)slot * a.n + id, anum ? tot * kInvSqrt2 : tot);
+        atomicAdd(rgv + (int64_t)id * kGradRow + slot, anum ? tot * kInvSqrt2 : tot);
       }
       if (kGeom) {
         const float nx = wave_sum_lane63(acc[G_NX]), ny = wave_sum_lane63(acc[G_NY]),
                     nz = wave_sum_lane63(acc[G_NZ]);
         if (lane == 63) {
-          atomicAdd(rg + (int64_t)G_NX * a.n + id, nx);
-          atomicAdd(rg + (int64_t)G_NY * a.n + id, ny);
-          atomicAdd(rg + (int64_t)G_NZ * a.n + id, nz);
+          float* q = rgn + (int64_t)id * kGradNrm;
+          atomicAdd(q, nx);
+          atomicAdd(q + 1, ny);
+          atomicAdd(q + 2, nz);
         }
       }
     }
@@ -491,15 +493,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
 
 // Clears the record gradients of the surfels in view v's visible list (the atomics add into them).
 __global__ __launch_bounds__(256) void k_zero_visible(const uint32_t* __restrict__ visible,
-                                                     const uint32_t* __restrict__ vstart, int64_t n, float* rg,
+                                                     const uint32_t* __restrict__ vstart, int64_t n, RecGrads rg,
                                                      int v0) {
   const int v = v0 + (int)blockIdx.y;
   const uint32_t e0 = vstart[v], e1 = vstart[v + 1];
-  float* r = rg + (int64_t)v * kGradFields * n;
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   for (uint32_t e = e0 + blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += gridDim.x * blockDim.x) {
-    const uint32_t i = visible[e];
+    const int64_t vi = (int64_t)v * n + visible[e];
+    float4* r = (float4*)(rg.row + vi * kGradRow);
 #pragma unroll
-    for (int f = 0; f < kGradFields; ++f) r[(int64_t)f * n + i] = 0.f;
+    for (int k = 0; k < 4; ++k) r[k] = z;
+    *(float4*)(rg.nrm + vi * kGradNrm) = z;
   }
 }
 
@@ -540,7 +544,7 @@ hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, cons
 
 hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                   int tiles_x, int tiles_y, const cgv2_image& img, const cgv2_image_grad& up,
-                                  float* rg, hipStream_t st) {
+                                  const cgv2::RecGrads& rg, hipStream_t st) {
   if (n > 0) {
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(cgv2::k_zero_visible, dim3(blocks, (unsigned)cams.count), dim3(256), 0, st, p.visible,

@@ -213,6 +213,23 @@ class Engine:
                                          ctypes.byref(up), ctypes.byref(grads.struct()), ptr(self.ws_bwd),
                                          self.ws_bwd.numel(), _stream()), "cgv2_render_bwd")
 
+    def backward_records(self, cams, d_rgb=None, d_depth=None, d_depth_med=None, d_normal=None, d_alpha=None,
+                         d_rgb_ssim=None):
+        """First stage of `backward`: pixel gradients -> record gradients (in this engine's workspace)."""
+        up = _lib.ImageGrad(ptr(d_rgb), ptr(d_depth), ptr(d_depth_med), ptr(d_normal), ptr(d_alpha),
+                            ptr(d_rgb_ssim))
+        check(_lib.lib().cgv2_render_bwd_records(ctypes.byref(self._proj), ctypes.byref(self._bins), cams, self.V,
+                                                 self.n, ctypes.byref(self._img), ctypes.byref(up), ptr(self.ws_bwd),
+                                                 self.ws_bwd.numel(), _stream()), "cgv2_render_bwd_records")
+
+    def project_backward(self, params: Params, cams, grads: Grads):
+        """Second stage of `backward`: record gradients -> parameter and view-space gradients."""
+        if grads.g_view_total.shape[0] < self.V:
+            raise ValueError("gradients hold fewer views than the engine")
+        check(_lib.lib().cgv2_project_bwd(ctypes.byref(params.struct()), ctypes.byref(self._proj), cams, self.V,
+                                          ptr(self.ws_bwd), self.ws_bwd.numel(), ctypes.byref(grads.struct()),
+                                          _stream()), "cgv2_project_bwd")
+
     def densify(self, params: Params, grads: Grads, state: DensifyState, omega=0.9, eta_min=0.05,
                 grad_threshold=2e-4):
         if state.scale.numel() < self.V or state.mask.numel() < self.n:

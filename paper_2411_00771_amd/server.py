@@ -69,6 +69,8 @@ class Server:
         self.max_w, self.max_h = max_width, max_height
         self.arena_bytes = int(arena_bytes)
         self.arena_used = 0
+        # intersections per pixel used to size a request's bins; raised to the largest ratio any
+        # finished request reported (x 1.1), so overflow re-admissions die out after a few requests
         self.ipp = float(intersections_per_pixel)
         self.slots = [_Slot(self.n, max_width, max_height, device) for _ in range(max_slots)]
         self.queue: Deque[Request] = collections.deque()
@@ -80,8 +82,7 @@ class Server:
     def submit(self, cam, arrival: Optional[float] = None) -> Request:
         if cam.width > self.max_w or cam.height > self.max_h:
             raise ValueError("resolution above the server's maximum")
-        cap = int(self.ipp * cam.width * cam.height) + 4096
-        r = Request(self._next, cam, time.perf_counter() if arrival is None else arrival, cap)
+        r = Request(self._next, cam, time.perf_counter() if arrival is None else arrival, 0)
         self._next += 1
         self.queue.append(r)
         return r
@@ -122,6 +123,7 @@ class Server:
             need = int(slot.host[1])
             slot.req = None
             self.arena_used -= r.est_bytes
+            self.ipp = max(self.ipp, 1.1 * need / (r.cam.width * r.cam.height))
             if over:
                 # bins too small: re-admit first with the reported size
                 r.capacity = int(need * 1.05) + 1024
@@ -137,6 +139,8 @@ class Server:
             if slot.req is not None or not self.queue:
                 continue
             r = self.queue[0]
+            if r.tries == 0:
+                r.capacity = int(self.ipp * r.cam.width * r.cam.height) + 4096
             est = self._estimate(r)
             if est > self.arena_bytes:
                 self.queue.popleft()

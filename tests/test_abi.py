@@ -43,6 +43,7 @@ def test_strerror_and_workspace_sizes():
     assert L.cgv2_bin_sort_workspace(1 << 20, 1, 6700, 10 ** 6) >= a + 4 * (10 ** 6 - 1000)
     assert L.cgv2_bin_sort_workspace(-1, 1, 10, 5) == 0 and L.cgv2_bin_sort_workspace(10, 0, 10, 5) == 0
     assert L.cgv2_render_bwd_workspace(1000, 2) >= 19 * 4 * 1000 * 2
+    assert L.cgv2_render_bwd_workspace(-1, 2) == 0 and L.cgv2_render_bwd_workspace(10, 0) == 0
     assert L.cgv2_loss_workspace(0, 10, 1) == 0
     assert L.cgv2_densify_workspace(10, 1) > 0
 
@@ -88,6 +89,13 @@ def test_argument_validation_returns_einval():
     # backward without the forward checkpoint
     assert L.cgv2_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(okbins), cams, 1, ctypes.byref(img),
                              ctypes.byref(up), ctypes.byref(g), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
+    assert L.cgv2_render_bwd_records(ctypes.byref(p), ctypes.byref(okbins), cams, 1, 10, ctypes.byref(img),
+                                     ctypes.byref(up), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
+    # parameter gradients missing
+    assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), cams, 1, ctypes.c_void_p(256), 1 << 30,
+                              ctypes.byref(g), None) == EINVAL
+    assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), cams, 1, ctypes.c_void_p(256), 1 << 30, None,
+                              None) == EINVAL
     prm = _lib.DensifyParams(0.9, 0.05, 2e-4)
     st = _lib.DensifyState()
     assert L.cgv2_densify_stats(ctypes.byref(s), ctypes.byref(p), ctypes.byref(g), 1, ctypes.byref(prm),
@@ -104,6 +112,15 @@ def test_small_workspace_returns_eworkspace():
     assert L.cgv2_bin_sort(ctypes.byref(p), ctypes.byref(cam), 1, 10, ctypes.byref(bins), ctypes.c_void_p(256),
                            need - 1, None) == _lib.CGV2_EWORKSPACE
     v = ctypes.c_void_p(256)
+    img = _lib.Image(*[v] * 8)
+    up = _lib.ImageGrad()
+    ws = L.cgv2_render_bwd_workspace(10, 1)
+    assert L.cgv2_render_bwd_records(ctypes.byref(p), ctypes.byref(bins), ctypes.byref(cam), 1, 10, ctypes.byref(img),
+                                     ctypes.byref(up), v, ws - 1, None) == _lib.CGV2_EWORKSPACE
+    s = _lib.Surfels(10, 3, *[v] * 5)
+    g = _lib.Grads(*[v] * 7)
+    assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(cam), 1, v, ws - 1, ctypes.byref(g),
+                              None) == _lib.CGV2_EWORKSPACE
     assert L.cgv2_loss(v, v, 1, 64, 64, 0.2, v, v, v, v, L.cgv2_loss_workspace(64, 64, 1) - 1,
                        None) == _lib.CGV2_EWORKSPACE
 

@@ -81,8 +81,13 @@ def test_mix_equals_alone(largest):
     (lv0, g0, st0), (lv1, g1, st1) = largest["run0"], largest["run1"]
     # the forward and the loss are deterministic; the gradients are sums of float atomics
     assert bool((lv0 == lv1).all())
+    # Two runs differ only in the order of float atomics: the group norms agree to 1e-4, and elementwise
+    # to the gradient tolerance (elements with heavy cancellation drift by more than 1e-4 relative; a lost
+    # or duplicated update would move an element by a whole term).
     for name in ("mean", "log_scale", "quat", "opacity_logit", "sh", "g_view_total", "g_view_ssim"):
-        grad_close(name, getattr(g1, name).cpu().numpy(), getattr(g0, name).cpu().numpy(), rel=1e-4)
+        a, b = getattr(g1, name).cpu().numpy().astype(np.float64), getattr(g0, name).cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b), name
+        grad_close(name, a, b)
     s0, s1 = st0.scale.cpu().numpy(), st1.scale.cpu().numpy()
     assert np.allclose(s0, s1, rtol=1e-4, atol=0)
     # masks may differ only for surfels at the threshold; count those at most 1e-5 of n

@@ -140,6 +140,23 @@ def _upstream(tiny, seed=3):
     return {k: v.astype(np.float32) for k, v in up.items()}
 
 
+def test_split_backward_equals_combined(tiny, cuda):
+    """cgv2_render_bwd_records followed by cgv2_project_bwd gives what cgv2_render_bwd gives (up to the
+    order of float atomics)."""
+    import torch
+    from paper_2411_00771_amd import raster
+    eng, params, cs = tiny["eng"], tiny["params"], tiny["cs"]
+    eng.forward(params, cs)
+    t = {k: torch.from_numpy(v).to(cuda)[None].contiguous() for k, v in _upstream(tiny, seed=11).items()}
+    g1, g2 = raster.Grads(params, 1), raster.Grads(params, 1)
+    eng.backward(params, cs, g1, **t)
+    eng.backward_records(cs, **t)
+    eng.project_backward(params, cs, g2)
+    torch.cuda.synchronize()
+    for name in ("mean", "log_scale", "quat", "opacity_logit", "sh", "g_view_total", "g_view_ssim"):
+        grad_close(name, getattr(g2, name).cpu().numpy(), getattr(g1, name).cpu().numpy(), rel=1e-5)
+
+
 def test_render_bwd_matches_oracle(tiny, cuda):
     import torch
     from paper_2411_00771_amd import raster
