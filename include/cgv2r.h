@@ -62,11 +62,14 @@ typedef struct {
   float bg[3];   /* background colour added with the final transmittance */
 } cgv2_camera;
 
-/* Surfel parameters (Sec. 3.1): n surfels, planar SoA float32.
- *   mean[3][n]; log_scale[2][n] (s = exp); quat[4][n] (w, x, y, z; normalised inside; the
- *   rotation's columns are t_u, t_v and the surfel normal); opacity_logit[n] (sigmoid);
- *   sh[(deg+1)^2][3][n] real SH coefficients, index l*l + l + m, colour =
- *   max(0, 0.5 + sum f Y) with the Condon-Shortley phase (Y_1^1 = -sqrt(3/4pi) x). */
+/* Surfel parameters (Sec. 3.1): n surfels, float32.
+ *   Geometry planar SoA: mean[3][n]; log_scale[2][n] (s = exp); quat[4][n] (w, x, y, z;
+ *   normalised inside; the rotation's columns are t_u, t_v and the surfel normal);
+ *   opacity_logit[n] (sigmoid).
+ *   Colour as one block per surfel: sh[n][(deg+1)^2][3] real SH coefficients, index l*l + l + m,
+ *   colour = max(0, 0.5 + sum f Y) with the Condon-Shortley phase (Y_1^1 = -sqrt(3/4pi) x).  (Only
+ *   the surfels visible in a view read their SH, so a per-surfel block is read whole instead of
+ *   one cache line per coefficient.) */
 typedef struct {
   int64_t n;
   int32_t sh_degree;
@@ -116,10 +119,16 @@ typedef struct {
  * transmittance exceeds 0.5; 0 if none), normal = sum w n (not normalised), alpha = 1 - T_final.
  * Checkpoint: T_final; last = one past the last contributing list entry; med = list index of
  * the median fragment (0xffffffff if none).  rgb/depth/depth_med/normal/alpha may be NULL;
- * T_final/last/med may be NULL when no backward pass follows. */
+ * T_final/last/med may be NULL when no backward pass follows.
+ * qmask (optional, [bins.capacity], indexed like bins.ids): per tile-list entry, bit k set when some
+ * pixel of quadrant k of the tile (k = (x >= 8) + 2 (y >= 8) within the 16x16 tile) takes the entry
+ * as a contributing fragment.  Written by cgv2_render_fwd for the entries it reaches; when the
+ * backward gets the same pointer it skips the entry/quadrant pairs without a contribution (same
+ * result, less work).  One byte per intersection; no per-fragment state. */
 typedef struct {
   float *rgb, *depth, *depth_med, *normal, *alpha, *T_final;
   uint32_t *last, *med;
+  uint8_t* qmask;
 } cgv2_image;
 
 /* Upstream gradients [V][c][H][W]; any may be NULL (= zero).  d_rgb_ssim is the part of d_rgb
@@ -129,7 +138,8 @@ typedef struct {
   const float* d_rgb_ssim;
 } cgv2_image_grad;
 
-/* Parameter gradients accumulate (+=) over views and calls: the caller zeroes them.
+/* Parameter gradients accumulate (+=) over views and calls: the caller zeroes them.  Each has the
+ * layout of its parameter (d_sh[n][(deg+1)^2][3]).
  * g_view_total / g_view_ssim [V][2][n] are overwritten: the gradient w.r.t. a rigid screen
  * translation of the surfel's image (the 2DGS form of the view-space position gradient of
  * Sec. 3.1), in NDC units (pixels * (W/2, H/2)), zero for surfels not visible in the view. */

@@ -45,7 +45,7 @@ class Bins(ctypes.Structure):
 
 class Image(ctypes.Structure):
     _fields_ = [("rgb", P), ("depth", P), ("depth_med", P), ("normal", P), ("alpha", P), ("T_final", P),
-                ("last", P), ("med", P)]
+                ("last", P), ("med", P), ("qmask", P)]
 
 
 class ImageGrad(ctypes.Structure):

@@ -113,8 +113,8 @@ __device__ __forceinline__ float reduce16_scatter(float (&v)[16]) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = v;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // Block -> tile mapping.  Hardware dispatches workgroup b to XCD b % 8.  Here XCD x receives the

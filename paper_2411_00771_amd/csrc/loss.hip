@@ -19,17 +19,36 @@ constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 
 struct Win { float g[11]; };
 
+// Block -> (tile x, tile y, plane).  Hardware sends block b to XCD b % 8; XCD x takes the column band
+// [x * band, (x + 1) * band) of every plane, row by row, so the halos that neighbouring tiles share
+// (left/right and above/below) are read through one L2.  Blocks past the right edge do nothing.
+struct LossGrid {
+  int tx, ty, band;
+};
+
+__device__ __forceinline__ bool loss_tile(const LossGrid& lg, int& bx, int& by, int& vc) {
+  const uint32_t b = blockIdx.x;
+  const uint32_t x = b % 8u, k = b / 8u;
+  const uint32_t per_plane = (uint32_t)(lg.band * lg.ty);
+  vc = (int)(k / per_plane);
+  const uint32_t r = k % per_plane;
+  by = (int)(r / (uint32_t)lg.band);
+  bx = (int)(x * (uint32_t)lg.band + r % (uint32_t)lg.band);
+  return bx < lg.tx;
+}
+
 __device__ __forceinline__ float at(const float* p, int W, int H, int x, int y) {
   return (x >= 0 && x < W && y >= 0 && y < H) ? p[(int64_t)y * W + x] : 0.f;
 }
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
-                                                  int H, Win win, float* __restrict__ maps,
+                                                  int H, Win win, LossGrid lg, float* __restrict__ maps,
                                                   double* __restrict__ partial) {
   __shared__ float sx[kSide][kSide], sy[kSide][kSide];
   __shared__ float hs[5][kSide][kTile];
   __shared__ double red[2][256];
-  const int bx = blockIdx.x, by = blockIdx.y, vc = blockIdx.z;  // vc = v * 3 + channel
+  int bx, by, vc;  // vc = v * 3 + channel
+  if (!loss_tile(lg, bx, by, vc)) return;
   const int64_t HW = (int64_t)W * H;
   const float* X = img + vc * HW;
   const float* Y = tgt + vc * HW;
@@ -93,18 +112,20 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ img,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int64_t blk = ((int64_t)vc * gridDim.y + by) * gridDim.x + bx;
+    const int64_t blk = ((int64_t)vc * lg.ty + by) * lg.tx + bx;
     partial[2 * blk] = red[0][0];
     partial[2 * blk + 1] = red[1][0];
   }
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
-                                                  int H, Win win, float lambda, const float* __restrict__ maps,
-                                                  float* __restrict__ d_img, float* __restrict__ d_ssim) {
+                                                  int H, Win win, LossGrid lg, float lambda,
+                                                  const float* __restrict__ maps, float* __restrict__ d_img,
+                                                  float* __restrict__ d_ssim) {
   __shared__ float sm[3][kSide][kSide];
   __shared__ float hs[3][kSide][kTile];
-  const int bx = blockIdx.x, by = blockIdx.y, vc = blockIdx.z;
+  int bx, by, vc;
+  if (!loss_tile(lg, bx, by, vc)) return;
   const int64_t HW = (int64_t)W * H;
   const float* Mp = maps + (int64_t)vc * 3 * HW;
   const int ox = bx * kTile - kR, oy = by * kTile - kR;
@@ -199,10 +220,15 @@ hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, in
   double g[11], gs = 0;
   for (int a = -5; a <= 5; ++a) { g[a + 5] = exp(-(double)(a * a) / (2 * 1.5 * 1.5)); gs += g[a + 5]; }
   for (int a = 0; a < 11; ++a) win.g[a] = (float)(g[a] / gs);
-  dim3 grid((unsigned)((W + 15) / 16), (unsigned)((H + 15) / 16), (unsigned)(3 * V));
-  hipLaunchKernelGGL(cgv2::k_ssim_fwd, grid, dim3(256), 0, st, img, tgt, W, H, win, maps, partial);
-  hipLaunchKernelGGL(cgv2::k_ssim_bwd, grid, dim3(256), 0, st, img, tgt, W, H, win, lambda, maps, d_img, d_ssim);
-  hipLaunchKernelGGL(cgv2::k_loss_final, dim3(1), dim3(256), 0, st, partial, (int64_t)grid.x * grid.y * 3, V,
+  cgv2::LossGrid lg;
+  lg.tx = (W + 15) / 16;
+  lg.ty = (H + 15) / 16;
+  lg.band = (lg.tx + 7) / 8;
+  const unsigned blocks = (unsigned)(8 * lg.band * lg.ty * 3 * V);
+  hipLaunchKernelGGL(cgv2::k_ssim_fwd, dim3(blocks), dim3(256), 0, st, img, tgt, W, H, win, lg, maps, partial);
+  hipLaunchKernelGGL(cgv2::k_ssim_bwd, dim3(blocks), dim3(256), 0, st, img, tgt, W, H, win, lg, lambda, maps, d_img,
+                     d_ssim);
+  hipLaunchKernelGGL(cgv2::k_loss_final, dim3(1), dim3(256), 0, st, partial, (int64_t)lg.tx * lg.ty * 3, V,
                      (int64_t)W * H, lambda, loss);
   return hipGetLastError();
 }

@@ -115,6 +115,34 @@ __device__ __forceinline__ void sh_grad_dot(const float* g, float x, float y, fl
   out[0] = gx; out[1] = gy; out[2] = gz;
 }
 
+// A surfel's SH block sh[i][K][3] (3K contiguous floats, 16-B aligned when 3K % 4 == 0).
+template <int N>
+__device__ __forceinline__ void load_row(const float* p, float (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+    const float4* q = (const float4*)p;
+#pragma unroll
+    for (int j = 0; j < N / 4; ++j) {
+      const float4 t = q[j];
+      v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = p[j];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void store_row(float* p, const float (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+    float4* q = (float4*)p;
+#pragma unroll
+    for (int j = 0; j < N / 4; ++j) q[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[j] = v[j];
+  }
+}
+
 struct Geom {
   double su, sv, o, qn[4], qlen, Rw[9];
   double pc[3];   // camera-space centre
@@ -266,12 +294,14 @@ __device__ __forceinline__ bool project_one(const cgv2_surfels& s, const DevCam&
   constexpr int K = (DEG + 1) * (DEG + 1);
   float Y[K];
   sh_basis<DEG>(g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
+  float f[3 * K];
+  load_row<3 * K>(s.sh + (int64_t)i * 3 * K, f);
   float col[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     float acc = 0.5f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(s.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], acc);
+    for (int k = 0; k < K; ++k) acc = fmaf(f[k * 3 + ch], Y[k], acc);
     col[ch] = fmaxf(acc, 0.f);
   }
   // record
@@ -301,7 +331,9 @@ __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, c
 // ------------------------------------------------------------------------------------------
 // One view (cams.c[0], view index cams.v0), one thread per entry of its visible list
 // (list[vstart[0] .. vstart[1])); each surfel appears once per list, so the parameter gradients are
-// added without atomics.
+// added without atomics.  Every load of a surfel (parameters, record gradients, the gradient values
+// being added to) is issued before its first store: the stores may alias the loaded arrays, so an
+// interleaved read-modify-write would cost one full memory round trip per element.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cams,
                                                       const uint32_t* __restrict__ list,
@@ -310,36 +342,47 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
   const int64_t n = s.n;
   const uint32_t e0 = vstart[0], e1 = vstart[1];
   constexpr int K = (DEG + 1) * (DEG + 1);
+  const int v = cams.v0;
+  const DevCam& c = cams.c[0];
   for (uint32_t e = e0 + blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += gridDim.x * blockDim.x) {
-  const int64_t i = list[e];
-  double dmu[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dls[2] = {0, 0}, dlogit = 0;
-  {
-    const int v = cams.v0;
-    const DevCam& c = cams.c[0];
-    float* gvt = gr.g_view_total ? gr.g_view_total + (int64_t)v * 2 * n : nullptr;
-    float* gvs = gr.g_view_ssim ? gr.g_view_ssim + (int64_t)v * 2 * n : nullptr;
+    const int64_t i = list[e];
+    // ---- loads
     float d[kGradFields];
     {
       const float4* r = (const float4*)(rg.row + ((int64_t)v * n + i) * kGradRow);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const float4 q = r[k];
-        d[4 * k] = q.x; d[4 * k + 1] = q.y; d[4 * k + 2] = q.z; d[4 * k + 3] = q.w;
+        d[4 * k] = q.x;
+        d[4 * k + 1] = q.y;
+        d[4 * k + 2] = q.z;
+        d[4 * k + 3] = q.w;
       }
       const float4 q = *(const float4*)(rg.nrm + ((int64_t)v * n + i) * kGradNrm);
-      d[G_NX] = q.x; d[G_NY] = q.y; d[G_NZ] = q.z;
+      d[G_NX] = q.x;
+      d[G_NY] = q.y;
+      d[G_NZ] = q.z;
     }
-    const float ndx = 0.5f * (float)c.W, ndy = 0.5f * (float)c.H;
-    if (gvt) { gvt[i] = d[G_CX] * ndx; gvt[n + i] = d[G_CY] * ndy; }
-    if (gvs) { gvs[i] = d[G_SCX] * ndx; gvs[n + i] = d[G_SCY] * ndy; }
-
+    float f[3 * K], gsh[3 * K];  // index k * 3 + channel
+    load_row<3 * K>(s.sh + i * 3 * K, f);
+    load_row<3 * K>(gr.d_sh + i * 3 * K, gsh);
+    float gmu[3], gq[4], gls[2], glo;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gmu[k] = gr.d_mean[k * n + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gq[k] = gr.d_quat[k * n + i];
+    gls[0] = gr.d_log_scale[i];
+    gls[1] = gr.d_log_scale[n + i];
+    glo = gr.d_opacity_logit[i];
     Geom g;
     load_geom(s, c, i, g);
+
+    // ---- record -> (alpha, beta, gamma) -> M; the common scale of the coefficients leaves every
+    // output unchanged, so it is held constant
+    double dmu[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0};
     Homog h;
     homography(g.M, h);
     const double* M = g.M;
-    // record -> (alpha, beta, gamma) -> M; the common scale of the coefficients leaves every
-    // output unchanged, so it is held constant
     const double sc = h.scale;
     const double dA11 = d[G_A11] * sc, dA12 = d[G_A12] * sc, dA21 = d[G_A21] * sc, dA22 = d[G_A22] * sc;
     const double dW0 = d[G_W0] * sc, dW1 = d[G_W1] * sc, dW2 = d[G_W2] * sc;
@@ -364,8 +407,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
     double vw[3][3];
     for (int k = 0; k < 3; ++k) {
       const double a = (double)c.fx * dM[k], b = (double)c.fy * dM[3 + k];
-      const double e = (double)c.cx * dM[k] + (double)c.cy * dM[3 + k] + dM[6 + k];
-      for (int r2 = 0; r2 < 3; ++r2) vw[k][r2] = (double)c.R[r2] * a + (double)c.R[3 + r2] * b + (double)c.R[6 + r2] * e;
+      const double e2 = (double)c.cx * dM[k] + (double)c.cy * dM[3 + k] + dM[6 + k];
+      for (int r2 = 0; r2 < 3; ++r2) vw[k][r2] = (double)c.R[r2] * a + (double)c.R[3 + r2] * b + (double)c.R[6 + r2] * e2;
     }
     double dsu = 0, dsv = 0, dR[9];
     for (int r2 = 0; r2 < 3; ++r2) {
@@ -392,11 +435,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
       const double dot = g.qn[0] * dqn[0] + g.qn[1] * dqn[1] + g.qn[2] * dqn[2] + g.qn[3] * dqn[3];
       for (int k = 0; k < 4; ++k) dq[k] += (dqn[k] - g.qn[k] * dot) / g.qlen;
     }
-    dls[0] += dsu * g.su;
-    dls[1] += dsv * g.sv;
-    dlogit += (double)d[G_OP] * g.o * (1 - g.o);
-    // colour through SH: coefficient gradients go to memory per view (+=), the direction
-    // gradient is contracted on the fly
+    const double dls0 = dsu * g.su, dls1 = dsv * g.sv;
+    const double dlogit = (double)d[G_OP] * g.o * (1 - g.o);
+    // colour through SH: the coefficient gradients are added per view, the direction gradient is
+    // contracted on the fly; a channel clamped at zero passes nothing
     float Y[K], gY[K];
     sh_basis<DEG>(g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
 #pragma unroll
@@ -405,29 +447,40 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float raw = 0.5f;
-      float f[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) raw = fmaf(f[k * 3 + ch], Y[k], raw);
+      const float dc = raw < 0.f ? 0.f : dcol[ch];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        f[k] = s.sh[(int64_t)(k * 3 + ch) * n + i];
-        raw = fmaf(f[k], Y[k], raw);
-      }
-      if (raw < 0.f) continue;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        gY[k] = fmaf(dcol[ch], f[k], gY[k]);
-        gr.d_sh[(int64_t)(k * 3 + ch) * n + i] += dcol[ch] * Y[k];
+        gY[k] = fmaf(dc, f[k * 3 + ch], gY[k]);
+        gsh[k * 3 + ch] = fmaf(dc, Y[k], gsh[k * 3 + ch]);
       }
     }
     float ddir[3];
     sh_grad_dot<DEG>(gY, g.dir[0], g.dir[1], g.dir[2], ddir);
     const float dd = ddir[0] * g.dir[0] + ddir[1] * g.dir[1] + ddir[2] * g.dir[2];
     for (int k = 0; k < 3; ++k) dmu[k] += (double)((ddir[k] - g.dir[k] * dd) / g.dist);
-  }
-  for (int k = 0; k < 3; ++k) gr.d_mean[k * n + i] += (float)dmu[k];
-  for (int k = 0; k < 4; ++k) gr.d_quat[k * n + i] += (float)dq[k];
-  gr.d_log_scale[i] += (float)dls[0];
-  gr.d_log_scale[n + i] += (float)dls[1];
-  gr.d_opacity_logit[i] += (float)dlogit;
+
+    // ---- stores
+    if (gr.g_view_total) {
+      float* gvt = gr.g_view_total + (int64_t)v * 2 * n;
+      gvt[i] = d[G_CX] * (0.5f * (float)c.W);
+      gvt[n + i] = d[G_CY] * (0.5f * (float)c.H);
+    }
+    if (gr.g_view_ssim) {
+      float* gvs = gr.g_view_ssim + (int64_t)v * 2 * n;
+      gvs[i] = d[G_SCX] * (0.5f * (float)c.W);
+      gvs[n + i] = d[G_SCY] * (0.5f * (float)c.H);
+    }
+    // channels clamped at zero store their unchanged values back
+    store_row<3 * K>(gr.d_sh + i * 3 * K, gsh);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gr.d_mean[k * n + i] = gmu[k] + (float)dmu[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gr.d_quat[k * n + i] = gq[k] + (float)dq[k];
+    gr.d_log_scale[i] = gls[0] + (float)dls0;
+    gr.d_log_scale[n + i] = gls[1] + (float)dls1;
+    gr.d_opacity_logit[i] = glo + (float)dlogit;
   }
 }
 
@@ -450,19 +503,21 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
   if (s.n == 0) return hipSuccess;
   const int64_t n = s.n;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  // g_view rows are overwritten: zero for surfels outside each view's list
+  const int64_t rows = (int64_t)cams.count * 2 * n;
+  const unsigned fill_blocks = (unsigned)std::min<int64_t>((rows + 255) / 256, 65535);
+  if (g.g_view_total)
+    hipLaunchKernelGGL(cgv2::k_fill<float>, dim3(fill_blocks), dim3(256), 0, st,
+                       g.g_view_total + (int64_t)cams.v0 * 2 * n, rows, 0.f);
+  if (g.g_view_ssim)
+    hipLaunchKernelGGL(cgv2::k_fill<float>, dim3(fill_blocks), dim3(256), 0, st,
+                       g.g_view_ssim + (int64_t)cams.v0 * 2 * n, rows, 0.f);
   for (int lv = 0; lv < cams.count; ++lv) {
     const int v = cams.v0 + lv;
     cgv2::CamPack one;
     one.c[0] = cams.c[lv];
     one.v0 = v;
     one.count = 1;
-    // g_view rows are overwritten: zero for surfels outside this view's list
-    if (g.g_view_total)
-      hipLaunchKernelGGL(cgv2::k_fill<float>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st,
-                         g.g_view_total + (int64_t)v * 2 * n, 2 * n, 0.f);
-    if (g.g_view_ssim)
-      hipLaunchKernelGGL(cgv2::k_fill<float>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st,
-                         g.g_view_ssim + (int64_t)v * 2 * n, 2 * n, 0.f);
     const uint32_t* list = p.visible;
     const uint32_t* cnt = p.visible_start + v;
     switch (s.sh_degree) {

@@ -45,8 +45,9 @@ struct Stage {
   uint32_t qm[64];
 };
 
+// qmask (optional): the forward's per-entry mask of quadrants with a contributing pixel, ANDed in.
 __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* rec, int64_t vn, int64_t n, uint32_t id,
-                                             int ox, int oy) {
+                                             int ox, int oy, const uint8_t* qmask, uint32_t idx) {
   // an id outside [0, n) (never produced by the binning) stages a record that reaches no quadrant
   const bool valid = (int64_t)id < n;
   const float4* r = (const float4*)(rec + (size_t)(vn + (valid ? id : 0u)) * kRec);
@@ -67,6 +68,7 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
     const int x0 = 8 * (k & 1), y0 = 8 * (k >> 1);
     if (i0 <= x0 + 7 && i1 >= x0 && j0 <= y0 + 7 && j1 >= y0) m |= 1u << k;
   }
+  if (qmask) m &= qmask[idx];
   s.qm[lane] = valid ? m : 0u;
 }
 
@@ -136,15 +138,17 @@ struct FwdState {
   bool done;
 };
 
+// Returns false when no pixel of the quadrant takes the entry (wave-uniform); true otherwise, which
+// covers every entry with a contributing fragment (a superset is all the reverse pass needs).
 template <int k>
-__device__ __forceinline__ void fwd_px(const LaneTerms& lt, const float4& q2, const float4& q3, const float4& q4,
+__device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, const float4& q3, const float4& q4,
                                        uint32_t e_idx, FwdState& f, unsigned long long& n_con) {
   Px e;
   eval_px<k>(lt, q2.y, e);
   // wave-uniform skip when no pixel of the quadrant takes this surfel; otherwise branch-free: a
   // contribution is a zero-weight no-op for pixels that skip or stop here
   const bool take = !f.done && e.alpha >= kAlphaMin;
-  if (__ballot(take) == 0) return;
+  if (__ballot(take) == 0) return false;
   const float a = take ? e.alpha : 0.f;
   const float Tn = f.T * (1.f - a);
   const bool stop = take && Tn < kTmin;
@@ -165,6 +169,7 @@ __device__ __forceinline__ void fwd_px(const LaneTerms& lt, const float4& q2, co
   f.med = m ? e_idx : f.med;
   f.last = upd ? e_idx + 1u : f.last;
   f.T = upd ? Tn : f.T;
+  return true;
 }
 
 // Quadrants of the tile with a running pixel (wave-uniform bit mask).
@@ -177,7 +182,8 @@ __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
 
 // kCount: instead of images, count the (pixel, list entry) pairs of the method (every entry a running
 // pixel meets, quadrant mask or not), the contributing pairs, and the pairs the reverse walks.
-template <bool kCount>
+// kMask: also write the per-entry quadrant mask img.qmask for the reverse pass.
+template <bool kCount, bool kMask>
 __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   __shared__ Stage s;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -209,12 +215,16 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     f[k].N[0] = f[k].N[1] = f[k].N[2] = 0.f;
   }
   const float lx0 = (float)lx + 0.5f, ly0 = (float)ly + 0.5f;
+  uint8_t* qmask = kMask ? a.img.qmask : nullptr;
   uint32_t qlive = live_quadrants(f);
   for (uint32_t base = start; base < end && qlive != 0; base += 64) {
     const uint32_t idx = base + lane;
-    if (idx < end) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy);
+    if (idx < end) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0);
     __syncthreads();
     const int cnt = (int)min(64u, end - base);
+    int reached = cnt;  // entries of this chunk the wave evaluated
+    // bit j of cq[k]: quadrant k had a taking pixel at entry base + j (scalar registers)
+    uint64_t cq0 = 0, cq1 = 0, cq2 = 0, cq3 = 0;
     for (int j = 0; j < cnt; ++j) {
       if (kCount) {
 #pragma unroll
@@ -226,16 +236,24 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         LaneTerms lt;
         lane_terms(lx0, ly0, q0, q1, q2, lt);
         const uint32_t e_idx = base + (uint32_t)j;
-        if (m & 1u) fwd_px<0>(lt, q2, q3, q4, e_idx, f[0], n_con);
-        if (m & 2u) fwd_px<1>(lt, q2, q3, q4, e_idx, f[1], n_con);
-        if (m & 4u) fwd_px<2>(lt, q2, q3, q4, e_idx, f[2], n_con);
-        if (m & 8u) fwd_px<3>(lt, q2, q3, q4, e_idx, f[3], n_con);
+        const uint64_t bit = 1ull << j;
+        if ((m & 1u) && fwd_px<0>(lt, q2, q3, q4, e_idx, f[0], n_con) && kMask) cq0 |= bit;
+        if ((m & 2u) && fwd_px<1>(lt, q2, q3, q4, e_idx, f[1], n_con) && kMask) cq1 |= bit;
+        if ((m & 4u) && fwd_px<2>(lt, q2, q3, q4, e_idx, f[2], n_con) && kMask) cq2 |= bit;
+        if ((m & 8u) && fwd_px<3>(lt, q2, q3, q4, e_idx, f[3], n_con) && kMask) cq3 |= bit;
       }
       if ((j & 15) == 15) {
         qlive = live_quadrants(f);
-        if (qlive == 0) break;
+        if (qlive == 0) {
+          reached = j + 1;
+          break;
+        }
       }
     }
+    // entries past 'reached' lie beyond every pixel's 'last': the reverse pass never reads them
+    if (kMask && lane < reached)
+      qmask[idx] = (uint8_t)(((cq0 >> lane) & 1u) | (((cq1 >> lane) & 1u) << 1) | (((cq2 >> lane) & 1u) << 2) |
+                             (((cq3 >> lane) & 1u) << 3));
     qlive = live_quadrants(f);
     __syncthreads();
   }
@@ -443,7 +461,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   for (uint32_t top = hi; top > start;) {
     const uint32_t lo = top - start > 64u ? top - 64u : start;
     const uint32_t idx = lo + lane;
-    if (idx < top) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy);
+    if (idx < top) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx);
     __syncthreads();
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
       const uint32_t e_idx = lo + (uint32_t)j;
@@ -530,7 +548,8 @@ hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const 
                                   int tiles_x, int tiles_y, const cgv2_image& img, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
   const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
-  hipLaunchKernelGGL(cgv2::k_render_fwd<false>, dim3(grid), dim3(64), 0, st, a);
+  if (img.qmask) hipLaunchKernelGGL((cgv2::k_render_fwd<false, true>), dim3(grid), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL((cgv2::k_render_fwd<false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -538,7 +557,7 @@ hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, cons
                                     int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, counters);
   const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
-  hipLaunchKernelGGL(cgv2::k_render_fwd<true>, dim3(grid), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((cgv2::k_render_fwd<true, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Sequence
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -28,7 +30,8 @@ def _stream():
 
 
 class Params:
-    """Surfel parameters on the device (planar SoA float32), from a generators' Scene or tensors."""
+    """Surfel parameters on the device, float32: geometry planar ([3][n], [2][n], [4][n], [n]) and the SH
+    coefficients as one block per surfel, sh[n][(deg+1)^2][3]."""
 
     def __init__(self, mean, log_scale, quat, opacity_logit, sh, sh_degree: int):
         self.mean, self.log_scale, self.quat = mean, log_scale, quat
@@ -39,8 +42,14 @@ class Params:
     @classmethod
     def from_scene(cls, scene, device="cuda"):
         f = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float32).contiguous()
-        return cls(f(scene.mean), f(scene.log_scale), f(scene.quat), f(scene.opacity_logit), f(scene.sh),
-                   scene.sh_degree)
+        return cls(f(scene.mean), f(scene.log_scale), f(scene.quat), f(scene.opacity_logit),
+                   f(np.ascontiguousarray(scene.sh.transpose(2, 0, 1))), scene.sh_degree)
+
+    @staticmethod
+    def sh_planar(sh) -> np.ndarray:
+        """[n][K][3] (this layout) -> [K][3][n] (the generators' and the oracle's layout)."""
+        a = sh.detach().cpu().numpy() if isinstance(sh, torch.Tensor) else np.asarray(sh)
+        return np.ascontiguousarray(a.transpose(1, 2, 0))
 
     @property
     def n(self) -> int:
@@ -146,7 +155,7 @@ class Engine:
         self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags), ptr(self.visible),
                                ptr(self.visible_start))
         self._img = _lib.Image(ptr(self.rgb), ptr(self.depth), ptr(self.depth_med), ptr(self.normal),
-                               ptr(self.alpha), ptr(self.T_final), ptr(self.last), ptr(self.med))
+                               ptr(self.alpha), ptr(self.T_final), ptr(self.last), ptr(self.med), ptr(self.qmask))
 
     def set_capacity(self, capacity: int):
         L = _lib.lib()
@@ -155,6 +164,11 @@ class Engine:
         self.ws_bin = torch.empty(L.cgv2_bin_sort_workspace(self.capacity, self.V, self.tiles, self.n), dtype=torch.uint8,
                                   device=self.device)
         self._bins = _lib.Bins(self.capacity, ptr(self.ids), ptr(self.ranges), ptr(self.status), ptr(self.needed))
+        # per list entry quadrant-contribution mask written by the forward for the backward
+        self.qmask = (torch.empty(max(self.capacity, 1), dtype=torch.uint8, device=self.device)
+                      if self.backward_enabled else None)
+        if hasattr(self, "_img"):
+            self._img.qmask = ptr(self.qmask)
 
     # ---- the five calls (+ loss) -------------------------------------------------------------
     def cams(self, cams: Sequence, exact: bool = True) -> ctypes.Array:

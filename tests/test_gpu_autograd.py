@@ -35,14 +35,17 @@ def _autograd_grads(sc, cams, targets, cuda):
     from paper_2411_00771_amd import raster
     eng = raster.Engine(sc.n, 64, 64, len(cams), capacity=1 << 18)
     cs = eng.cams(cams)
+    # the SH block of each surfel is contiguous on the device: [n][K][3]
     ts = [torch.from_numpy(getattr(sc, k)).to(cuda).requires_grad_(True)
-          for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")]
+          for k in ("mean", "log_scale", "quat", "opacity_logit")]
+    ts.append(torch.from_numpy(np.ascontiguousarray(sc.sh.transpose(2, 0, 1))).to(cuda).requires_grad_(True))
     rgb, depth, dmed, normal, alpha = raster.rasterize(ts, eng, cs, sc.sh_degree)
     loss = raster.L1SSIMLoss.apply(rgb, torch.from_numpy(np.stack(targets)).to(cuda), eng, 0.2)
     loss.backward()
     torch.cuda.synchronize()
     assert eng.status.item() == 0
-    return eng, [t.grad.cpu().numpy() for t in ts], loss.item()
+    grads = [t.grad.cpu().numpy() for t in ts[:4]] + [raster.Params.sh_planar(ts[4].grad)]
+    return eng, grads, loss.item()
 
 
 def test_autograd_matches_oracle_and_fd(cuda):
