@@ -2,17 +2,20 @@
 //
 // Instead of a global LSD radix sort over (view | tile | depth) keys, intersections are bucketed
 // by tile directly:
-//   surfel scan   exclusive prefix sum of every (surfel, view)'s tile count (from its rect)
-//   k_stage       one thread per (surfel, view): writes (tile, depth bits << 32 | id) of each
-//                 covered tile into its own slice and counts the tile (fire-and-forget atomics)
-//   tile scan     exclusive prefix sum of the V * tiles counters -> ranges and cursors
-//   k_place       one thread per intersection: a returning atomic on the tile cursor places the key
+//   surfel scan   one fused three-kernel pass over every (view, surfel): the exclusive prefix sum of
+//                 its tile count (from its rect) and the compaction of the visible ones into per-view
+//                 lists, plus the capacity check
+//   k_stage       groups of lanes per visible surfel: for each covered tile, a returning atomic on the
+//                 tile's counter gives the entry's rank within the tile; (tile, rank, depth bits << 32 |
+//                 id) goes to the surfel's own slice
+//   k_tile_scan   one workgroup: exclusive prefix sum of the V * tiles counters -> ranges
+//   k_place       one thread per intersection: keys[ranges[tile] + rank] = key (no atomics)
 //   k_sort_small  one workgroup per tile: LDS bitonic sort of lists up to kSmall entries
 //   k_sort_big    lists up to kBig entries in 128 KB of LDS; longer lists are sorted in kBig chunks
 //                 and merged in global memory by rank (binary search)
-// (depth bits, id) is unique within a tile, so the atomic placement order does not matter and the
-// result is deterministic and bit-exact.  HBM traffic is about 12 B staged + 12 B read + 8 B placed
-// + 8 B read + 4 B written per intersection.
+// (depth bits, id) is unique within a tile, so the order in which the atomics hand out ranks does not
+// matter: the result is deterministic and bit-exact.  HBM traffic is about 16 B staged + 16 B read +
+// 8 B placed + 8 B read + 4 B written per intersection.
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
@@ -38,19 +41,6 @@ __device__ __forceinline__ uint32_t rect_count(const uint16_t* r4) {
   return (tx1 - tx0) * (ty1 - ty0);
 }
 
-// scan inputs: a u32 array, the tile counts of the rects, or the rects' non-empty bits
-struct ScanIn {
-  const uint32_t* u32;
-  const uint16_t* rect;
-  int nonzero;
-  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
-    if (u32) return u32[i];
-    const uint32_t c = rect_count(rect + 4 * i);
-    return nonzero ? (c != 0u) : c;
-  }
-};
-
-
 // block-wide exclusive scan of kScanChunk values held kScanItems per thread; returns the total
 __device__ __forceinline__ uint64_t block_scan(uint64_t (&vals)[kScanItems], uint64_t* lds) {
   uint64_t s = 0;
@@ -71,28 +61,12 @@ __device__ __forceinline__ uint64_t block_scan(uint64_t (&vals)[kScanItems], uin
   return total;
 }
 
-// pass 1: per-chunk sums
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(ScanIn in, int64_t m, uint64_t* __restrict__ sums) {
+// pass 2 of the surfel scan: workgroup 0 scans the chunk sums of the counts in place, workgroup 1
+// those of the visible flags (any count, kScanChunk at a time); totals[blockIdx.x] = grand total
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ sums0, uint64_t* __restrict__ sums1,
+                                                         int64_t nb, uint64_t* __restrict__ totals) {
   __shared__ uint64_t lds[kScanBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint64_t s = 0;
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
-    if (idx < m) s += in(idx);
-  }
-  lds[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = lds[0];
-}
-
-// pass 2: one workgroup scans the chunk sums in place (any count, kScanChunk at a time)
-__global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ sums, int64_t nb,
-                                                         uint64_t* __restrict__ total) {
-  __shared__ uint64_t lds[kScanBlock];
+  uint64_t* sums = blockIdx.x == 0 ? sums0 : sums1;
   uint64_t carry = 0;
   for (int64_t base = 0; base < nb; base += kScanChunk) {
     const int64_t b0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -103,77 +77,89 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ 
       if (b0 + k < nb) sums[b0 + k] = vals[k] + carry;
     carry += tot;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-// pass 3: scan each chunk with its offset; out[m] = total (clamped to u32).  When 'cursor' is set
-// it receives a copy.  When 'capacity' >= 0 the total is checked against it.
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(ScanIn in, int64_t m, const uint64_t* __restrict__ sums,
-                                                           const uint64_t* __restrict__ total,
-                                                           uint32_t* __restrict__ out, uint32_t* __restrict__ cursor,
-                                                           int64_t capacity, int32_t* __restrict__ status,
-                                                           int64_t* __restrict__ needed) {
-  __shared__ uint64_t lds[kScanBlock];
-  const uint64_t carry = sums[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  uint64_t vals[kScanItems];
-  for (int k = 0; k < kScanItems; ++k) vals[k] = base + k < m ? in(base + k) : 0;
-  block_scan(vals, lds);
+// pass 1 of the surfel scan: per-chunk sums of the tile counts and of the visible flags
+__global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __restrict__ rect, int64_t m,
+                                                            uint64_t* __restrict__ sums_cnt,
+                                                            uint64_t* __restrict__ sums_vis) {
+  __shared__ uint64_t lds[2][kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint64_t c = 0, f = 0;
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < m) {
-      const uint64_t v = vals[k] + carry;
-      const uint32_t v32 = (uint32_t)(v > 0xffffffffull ? 0xffffffffull : v);
-      out[base + k] = v32;
-      if (cursor) cursor[base + k] = v32;
+    const int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
+    if (idx < m) {
+      const uint32_t t = rect_count(rect + 4 * idx);
+      c += t;
+      f += t != 0u;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint64_t K = *total;
-    out[m] = (uint32_t)(K > 0xffffffffull ? 0xffffffffull : K);
-    if (capacity >= 0) {
-      *needed = (int64_t)K;
-      if ((int64_t)K > capacity) *status = 1;
+  lds[0][threadIdx.x] = c;
+  lds[1][threadIdx.x] = f;
+  __syncthreads();
+  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      lds[0][threadIdx.x] += lds[0][threadIdx.x + off];
+      lds[1][threadIdx.x] += lds[1][threadIdx.x + off];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sums_cnt[blockIdx.x] = lds[0][0];
+    sums_vis[blockIdx.x] = lds[1][0];
   }
 }
 
-// compaction: visible[pos] = surfel id of every (view, surfel) with a non-empty rect, in (view, id)
-// order; vstart[v] = first entry of view v, vstart[V] = total
-__global__ __launch_bounds__(kScanBlock) void k_visible_apply(ScanIn in, int64_t m, int64_t n,
-                                                              const uint64_t* __restrict__ sums,
-                                                              const uint64_t* __restrict__ total,
-                                                              uint32_t* __restrict__ visible,
-                                                              uint32_t* __restrict__ vstart, int V) {
+// pass 3 of the surfel scan: soff[e] = first staged slot of (view, surfel) e, soff[m] = total;
+// visible[pos] = surfel id of every (view, surfel) with a non-empty rect in (view, id) order,
+// vstart[v] = first entry of view v, vstart[V] = total; the total is checked against the capacity
+__global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
+    const uint16_t* __restrict__ rect, int64_t m, int64_t n, const uint64_t* __restrict__ sums_cnt,
+    const uint64_t* __restrict__ sums_vis, const uint64_t* __restrict__ totals, uint32_t* __restrict__ soff,
+    uint32_t* __restrict__ visible, uint32_t* __restrict__ vstart, int V, int64_t capacity,
+    int32_t* __restrict__ status, int64_t* __restrict__ needed) {
   __shared__ uint64_t lds[kScanBlock];
-  const uint64_t carry = sums[blockIdx.x];
+  const uint64_t carry_c = sums_cnt[blockIdx.x], carry_v = sums_vis[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  uint64_t vals[kScanItems];
+  uint64_t vc[kScanItems], vv[kScanItems];
   uint32_t flag[kScanItems];
   for (int k = 0; k < kScanItems; ++k) {
-    flag[k] = base + k < m ? in(base + k) : 0u;
-    vals[k] = flag[k];
+    const uint32_t c = base + k < m ? rect_count(rect + 4 * (base + k)) : 0u;
+    vc[k] = c;
+    flag[k] = c != 0u;
+    vv[k] = flag[k];
   }
-  block_scan(vals, lds);
+  block_scan(vc, lds);
+  block_scan(vv, lds);
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t e = base + k;
     if (e >= m) continue;
-    const uint32_t pos = (uint32_t)(vals[k] + carry);
+    const uint64_t c = vc[k] + carry_c;
+    soff[e] = (uint32_t)(c > 0xffffffffull ? 0xffffffffull : c);
+    const uint32_t pos = (uint32_t)(vv[k] + carry_v);
     const int64_t i = e % n;
     if (flag[k]) visible[pos] = (uint32_t)i;
     if (i == 0) vstart[e / n] = pos;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) vstart[V] = (uint32_t)*total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint64_t K = totals[0];
+    soff[m] = (uint32_t)(K > 0xffffffffull ? 0xffffffffull : K);
+    vstart[V] = (uint32_t)totals[1];
+    *needed = (int64_t)K;
+    if ((int64_t)K > capacity) *status = 1;
+  }
 }
 
-// Groups of 8 lanes take one visible surfel of view blockIdx.y each and spread its tiles over the
+// Groups of 32 lanes take one visible surfel of view blockIdx.y each and spread its tiles over the
 // group, so a surfel that covers hundreds of tiles does not hold up a wave.
-constexpr int kGroup = 8;
+constexpr int kGroup = 32;
 __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect, const float* __restrict__ rec,
                                                int64_t n, int tiles_x, int tiles_per_view,
                                                const uint32_t* __restrict__ visible,
                                                const uint32_t* __restrict__ vstart,
                                                const uint32_t* __restrict__ soff, uint32_t* __restrict__ cnt,
-                                               uint32_t* __restrict__ st_tile, uint64_t* __restrict__ st_key,
+                                               uint2* __restrict__ st_pos, uint64_t* __restrict__ st_key,
                                                const int32_t* __restrict__ status) {
   const int v = blockIdx.y;
   if (*status != 0) return;
@@ -190,24 +176,88 @@ __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect
     const uint32_t w = tx1 - tx0, total = w * (ty1 - ty0);
     const uint64_t key = ((uint64_t)__float_as_uint(rec[vi * kRec + R_ZC]) << 32) | i;
     const uint32_t o = soff[vi];
-    for (uint32_t k = g; k < total; k += kGroup) {
-      const uint32_t t = tbase + (ty0 + k / w) * tiles_x + tx0 + k % w;
-      st_tile[o + k] = t;
-      st_key[o + k] = key;
-      atomicAdd(cnt + t, 1u);
+    // four independent returning atomics in flight per lane before their results are used
+    for (uint32_t k0 = g; k0 < total; k0 += 4 * kGroup) {
+      uint32_t t[4], r[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t k = k0 + (uint32_t)j * kGroup;
+        t[j] = tbase + (ty0 + k / w) * tiles_x + tx0 + k % w;
+        r[j] = k < total ? atomicAdd(cnt + t[j], 1u) : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t k = k0 + (uint32_t)j * kGroup;
+        if (k < total) {
+          st_pos[o + k] = make_uint2(t[j], r[j]);
+          st_key[o + k] = key;
+        }
+      }
     }
   }
 }
 
+// One workgroup: ranges[t] = exclusive prefix sum of cnt (m tile counters), ranges[m] = total.
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan(const uint32_t* __restrict__ cnt, int64_t m,
+                                                          uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t lds[kScanBlock];
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < m; base += kScanChunk) {
+    const int64_t b0 = base + (int64_t)threadIdx.x * kScanItems;
+    uint64_t vals[kScanItems];
+    for (int k = 0; k < kScanItems; ++k) vals[k] = b0 + k < m ? cnt[b0 + k] : 0;
+    const uint64_t tot = block_scan(vals, lds);
+    for (int k = 0; k < kScanItems; ++k)
+      if (b0 + k < m) ranges[b0 + k] = (uint32_t)(vals[k] + carry);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ranges[m] = (uint32_t)carry;
+}
+
+// Multi-workgroup form of the tile scan for many tiles: chunk sums, then (after k_scan_top) each chunk
+// scanned with its carry.
+__global__ __launch_bounds__(kScanBlock) void k_u32_sums(const uint32_t* __restrict__ a, int64_t m,
+                                                         uint64_t* __restrict__ sums) {
+  __shared__ uint64_t lds[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint64_t c = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
+    if (idx < m) c += a[idx];
+  }
+  lds[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = lds[0];
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_u32_apply(const uint32_t* __restrict__ a, int64_t m,
+                                                          const uint64_t* __restrict__ sums,
+                                                          const uint64_t* __restrict__ total,
+                                                          uint32_t* __restrict__ out) {
+  __shared__ uint64_t lds[kScanBlock];
+  const uint64_t carry = sums[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint64_t vals[kScanItems];
+  for (int k = 0; k < kScanItems; ++k) vals[k] = base + k < m ? a[base + k] : 0;
+  block_scan(vals, lds);
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < m) out[base + k] = (uint32_t)(vals[k] + carry);
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = (uint32_t)*total;
+}
+
 __global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ soff_total,
-                                               const uint32_t* __restrict__ st_tile,
-                                               const uint64_t* __restrict__ st_key, uint32_t* __restrict__ cursor,
-                                               uint64_t* __restrict__ keys, const int32_t* __restrict__ status) {
+                                               const uint2* __restrict__ st_pos, const uint64_t* __restrict__ st_key,
+                                               const uint32_t* __restrict__ ranges, uint64_t* __restrict__ keys,
+                                               const int32_t* __restrict__ status) {
   if (*status != 0) return;
   const uint32_t K = *soff_total;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
-    const uint32_t pos = atomicAdd(cursor + st_tile[e], 1u);
-    keys[pos] = st_key[e];
+    const uint2 tp = st_pos[e];
+    keys[ranges[tp.x] + tp.y] = st_key[e];
   }
 }
 
@@ -326,23 +376,24 @@ __global__ __launch_bounds__(1024) void k_sort_big(const uint32_t* __restrict__ 
 static int64_t scan_blocks(int64_t m) { return (m + cgv2::kScanChunk - 1) / cgv2::kScanChunk; }
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off) {
-  // off: [0] cnt (u32, m), [1] cursor (u32, m), [2] scan sums (u64), [3] big_list (u32, m),
-  //      [4] big_count + scan totals, [5] keys (u64, capacity), [6] staged keys / merge scratch
-  //      (u64, capacity), [7] staged tiles (u32, capacity), [8] surfel offsets (u32, V n + 1)
+  // off: [0] tile counters (u32, m) followed by the big-list count, [1] chunk sums of the surfel
+  //      scan (2 x u64 arrays), [2] big_list (u32, m), [3] scan totals (u64 x 2), [4] keys (u64,
+  //      capacity), [5] staged keys / merge scratch (u64, capacity), [6] staged (tile, rank) (u32 x 2,
+  //      capacity), [7] surfel offsets (u32, V n + 1), [8] chunk sums of the tile scan (u64)
   const int64_t m = (int64_t)V * tiles;
   const int64_t vn = (int64_t)V * n;
-  const int64_t nsb = scan_blocks(m > vn ? m : vn);
+  const int64_t nsb = scan_blocks(vn > 0 ? vn : 1);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
-  off[0] = take(4 * (size_t)m);
-  off[1] = take(4 * (size_t)m);
-  off[2] = take(8 * (size_t)(nsb + 1));
-  off[3] = take(4 * (size_t)m);
-  off[4] = take(64);
+  off[0] = take(4 * (size_t)(m + 1));
+  off[1] = take(16 * (size_t)(nsb + 1));
+  off[2] = take(4 * (size_t)m);
+  off[3] = take(64);
+  off[4] = take(8 * (size_t)capacity);
   off[5] = take(8 * (size_t)capacity);
   off[6] = take(8 * (size_t)capacity);
-  off[7] = take(4 * (size_t)capacity);
-  off[8] = take(4 * (size_t)(vn + 1));
+  off[7] = take(4 * (size_t)(vn + 1));
+  off[8] = take(8 * (size_t)(scan_blocks(m) + 1));
   return o;
 }
 
@@ -352,49 +403,49 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   const int tiles = tiles_x * tiles_y;
   const int64_t m = (int64_t)V * tiles;
   const int64_t vn = (int64_t)V * n;
-  size_t off[9];
+  size_t off[kBinsortOffs];
   cgv2_binsort_ws_layout(b.capacity, V, tiles, n, off);
   char* w = (char*)ws;
   uint32_t* cnt = (uint32_t*)(w + off[0]);
-  uint32_t* cursor = (uint32_t*)(w + off[1]);
-  uint64_t* sums = (uint64_t*)(w + off[2]);
-  uint32_t* big_list = (uint32_t*)(w + off[3]);
-  uint32_t* big_count = (uint32_t*)(w + off[4]);
-  uint64_t* totals = (uint64_t*)(w + off[4] + 8);  // [0] surfel scan, [1] tile scan, [2] visible scan
-  uint64_t* keys = (uint64_t*)(w + off[5]);
-  uint64_t* stk = (uint64_t*)(w + off[6]);
-  uint32_t* stt = (uint32_t*)(w + off[7]);
-  uint32_t* soff = (uint32_t*)(w + off[8]);
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, cnt, m, 0u);
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, big_count, (int64_t)1, 0u);
-  // surfel offsets, total and overflow check
-  ScanIn sin{nullptr, p.rect, 0};
-  const int64_t nbs = scan_blocks(vn > 0 ? vn : 1);
-  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nbs), dim3(kScanBlock), 0, st, sin, vn, sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, sums, nbs, totals);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbs), dim3(kScanBlock), 0, st, sin, vn, sums, totals, soff,
-                     (uint32_t*)nullptr, b.capacity, b.status, b.needed);
-  // visible lists (consumed by the staging here and by the reverse pass)
+  uint32_t* big_count = cnt + m;
+  const int64_t nsb = scan_blocks(vn > 0 ? vn : 1);
+  uint64_t* sums_cnt = (uint64_t*)(w + off[1]);
+  uint64_t* sums_vis = sums_cnt + nsb + 1;
+  uint32_t* big_list = (uint32_t*)(w + off[2]);
+  uint64_t* totals = (uint64_t*)(w + off[3]);
+  uint64_t* keys = (uint64_t*)(w + off[4]);
+  uint64_t* stk = (uint64_t*)(w + off[5]);
+  uint2* stp = (uint2*)(w + off[6]);
+  uint32_t* soff = (uint32_t*)(w + off[7]);
+  // tile counters and the big-list count
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)std::min<int64_t>((m + 256) / 256, 65535)), dim3(256), 0, st,
+                     cnt, m + 1, 0u);
   if (n > 0) {
-    ScanIn vin{nullptr, p.rect, 1};
-    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nbs), dim3(kScanBlock), 0, st, vin, vn, sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, sums, nbs, totals + 2);
-    hipLaunchKernelGGL(k_visible_apply, dim3((unsigned)nbs), dim3(kScanBlock), 0, st, vin, vn, n, sums, totals + 2,
-                       p.visible, p.visible_start, V);
+    // surfel offsets, visible lists (consumed by the staging here and by the reverse pass), total and
+    // overflow check
+    hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis);
+    hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
+    hipLaunchKernelGGL(k_surfel_apply, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, n, sums_cnt,
+                       sums_vis, totals, soff, p.visible, p.visible_start, V, b.capacity, b.status, b.needed);
     const unsigned blocks = (unsigned)std::min<int64_t>((n * kGroup + 255) / 256, 2048);
     hipLaunchKernelGGL(k_stage, dim3(blocks, (unsigned)V), dim3(256), 0, st, p.rect, p.rec, n, tiles_x, tiles,
-                       p.visible, p.visible_start, soff, cnt, stt, stk, b.status);
+                       p.visible, p.visible_start, soff, cnt, stp, stk, b.status);
   } else {
+    // no surfels: empty lists, zero intersections
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, p.visible_start, (int64_t)V + 1, 0u);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, soff, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(256), 0, st, b.needed, (int64_t)1, (int64_t)0);
   }
-  // tile ranges and cursors
-  ScanIn tin{cnt, nullptr, 0};
   const int64_t nbt = scan_blocks(m);
-  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nbt), dim3(kScanBlock), 0, st, tin, m, sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, sums, nbt, totals + 1);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbt), dim3(kScanBlock), 0, st, tin, m, sums, totals + 1, b.ranges,
-                     cursor, (int64_t)-1, b.status, b.needed);
-  hipLaunchKernelGGL(k_place, dim3(2048), dim3(256), 0, st, soff + vn, stt, stk, cursor, keys, b.status);
+  if (nbt <= 16) {
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanBlock), 0, st, cnt, m, b.ranges);
+  } else {
+    uint64_t* ts = (uint64_t*)(w + off[8]);
+    hipLaunchKernelGGL(k_u32_sums, dim3((unsigned)nbt), dim3(kScanBlock), 0, st, cnt, m, ts);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, ts, ts, nbt, totals + 2);
+    hipLaunchKernelGGL(k_u32_apply, dim3((unsigned)nbt), dim3(kScanBlock), 0, st, cnt, m, ts, totals + 2, b.ranges);
+  }
+  hipLaunchKernelGGL(k_place, dim3(2048), dim3(256), 0, st, soff + vn, stp, stk, b.ranges, keys, b.status);
   hipLaunchKernelGGL(k_sort_small, dim3((unsigned)m), dim3(256), 0, st, b.ranges, (int)m, keys, b.ids, big_list,
                      big_count, b.status);
   hipLaunchKernelGGL(k_sort_big, dim3(256), dim3(1024), 0, st, b.ranges, keys, stk, b.ids, big_list, big_count,

@@ -133,7 +133,7 @@ int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2
 
 size_t cgv2_bin_sort_workspace(int64_t capacity, int32_t V, int32_t tiles_per_view, int64_t n) {
   if (capacity < 0 || V < 1 || tiles_per_view < 1 || n < 0) return 0;
-  size_t off[9];
+  size_t off[kBinsortOffs];
   return cgv2_binsort_ws_layout(capacity, V, tiles_per_view, n, off);
 }
 
@@ -176,7 +176,7 @@ int cgv2_render_count(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_c
 
 size_t cgv2_loss_workspace(int32_t width, int32_t height, int32_t V) {
   if (width <= 0 || height <= 0 || V < 1) return 0;
-  size_t off[2];
+  size_t off[kLossOffs];
   return cgv2_loss_ws_layout(width, height, V, off);
 }
 
@@ -222,7 +222,7 @@ int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_ca
 
 size_t cgv2_densify_workspace(int64_t n, int32_t V) {
   if (n < 0 || V < 1) return 0;
-  size_t off[1];
+  size_t off[kDensifyOffs];
   return cgv2_densify_ws_layout(n, V, off);
 }
 

@@ -11,6 +11,9 @@ hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams,
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
+// Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
+constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2;
+
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
                                 void* ws, hipStream_t st);

@@ -5,7 +5,8 @@
 //                visible surfels, tree-reduced in FP64 in a fixed order
 // k_dgd_final    one workgroup reduces each view's block partials in a fixed order into
 //                scale_v = max(omega a_tot / a_ssim, 1) (deterministic)
-// k_densify      updates the per-surfel state, the masks and the counters
+// k_densify      updates the per-surfel state and the masks; per-workgroup counter partials
+// k_count_final  one workgroup adds the partials to the counters (no same-address atomics)
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
@@ -78,11 +79,13 @@ __global__ __launch_bounds__(kDBlock) void k_dgd_final(const double* __restrict_
   }
 }
 
+constexpr int kCounters = 6;
+
 __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8_t* __restrict__ flags,
                                                      const float* __restrict__ radius, const float* __restrict__ gt,
                                                      const float* __restrict__ gs, int V,
                                                      const float* __restrict__ scale_ws, cgv2_densify_params prm,
-                                                     cgv2_densify_state st) {
+                                                     cgv2_densify_state st, uint32_t* __restrict__ cpart) {
   __shared__ uint32_t cnt_s[8];
   const int64_t n = s.n;
   if (threadIdx.x < 8) cnt_s[threadIdx.x] = 0;
@@ -130,15 +133,39 @@ __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8
     if (cand) atomicAdd(&cnt_s[5], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 6 && cnt_s[threadIdx.x]) atomicAdd(st.counters + threadIdx.x, cnt_s[threadIdx.x]);
+  if (threadIdx.x < kCounters) cpart[(int64_t)blockIdx.x * kCounters + threadIdx.x] = cnt_s[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kDBlock) void k_count_final(const uint32_t* __restrict__ cpart, int nblocks,
+                                                         uint32_t* __restrict__ counters) {
+  __shared__ uint32_t red[kCounters][kDBlock];
+  uint32_t a[kCounters] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 8
+  for (int b = threadIdx.x; b < nblocks; b += kDBlock)
+#pragma unroll
+    for (int c = 0; c < kCounters; ++c) a[c] += cpart[(int64_t)b * kCounters + c];
+#pragma unroll
+  for (int c = 0; c < kCounters; ++c) red[c][threadIdx.x] = a[c];
+  __syncthreads();
+  for (int off = kDBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int c = 0; c < kCounters; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < kCounters) counters[threadIdx.x] += red[threadIdx.x][0];
 }
 
 }  // namespace cgv2
 
 size_t cgv2_densify_ws_layout(int64_t n, int V, size_t* off) {
+  // off: [0] scale per view (f32, V), [1] counter partials (u32, 6 per k_densify workgroup); the DGD
+  // partial sums (f64) start at 0
   const int64_t nb = (n + cgv2::kDBlock * cgv2::kDItems - 1) / (cgv2::kDBlock * cgv2::kDItems);
+  const int64_t nbd = (n + cgv2::kDBlock - 1) / cgv2::kDBlock;
   off[0] = ((size_t)(2 * sizeof(double) * (size_t)(nb > 0 ? nb : 1) * V + 255) & ~(size_t)255);
-  return off[0] + (((size_t)V * sizeof(float) + 255) & ~(size_t)255);
+  off[1] = off[0] + (((size_t)V * sizeof(float) + 255) & ~(size_t)255);
+  return off[1] + (((size_t)cgv2::kCounters * sizeof(uint32_t) * (size_t)(nbd > 0 ? nbd : 1) + 255) & ~(size_t)255);
 }
 
 hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const cgv2_grads& g, int V,
@@ -147,18 +174,20 @@ hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const 
   const int64_t n = s.n;
   const int nb = (int)((n + cgv2::kDBlock * cgv2::kDItems - 1) / (cgv2::kDBlock * cgv2::kDItems));
   const int nbp = nb > 0 ? nb : 1;
-  size_t off[1];
+  size_t off[kDensifyOffs];
   cgv2_densify_ws_layout(n, V, off);
   double* partial = (double*)ws;
   float* scale_ws = (float*)((char*)ws + off[0]);
+  uint32_t* cpart = (uint32_t*)((char*)ws + off[1]);
   hipLaunchKernelGGL(cgv2::k_dgd_partial, dim3((unsigned)nbp, (unsigned)V), dim3(cgv2::kDBlock), 0, stream, p.flags,
                      g.g_view_total, g.g_view_ssim, n, partial, nbp, st.counters);
   hipLaunchKernelGGL(cgv2::k_dgd_final, dim3(1), dim3(cgv2::kDBlock), 0, stream, partial, nbp, V, prm.omega, scale_ws,
                      st.scale);
   if (n > 0) {
-    hipLaunchKernelGGL(cgv2::k_densify, dim3((unsigned)((n + cgv2::kDBlock - 1) / cgv2::kDBlock)),
-                       dim3(cgv2::kDBlock), 0, stream, s, p.flags, p.radius, g.g_view_total, g.g_view_ssim, V,
-                       scale_ws, prm, st);
+    const int nbd = (int)((n + cgv2::kDBlock - 1) / cgv2::kDBlock);
+    hipLaunchKernelGGL(cgv2::k_densify, dim3((unsigned)nbd), dim3(cgv2::kDBlock), 0, stream, s, p.flags, p.radius,
+                       g.g_view_total, g.g_view_ssim, V, scale_ws, prm, st, cpart);
+    hipLaunchKernelGGL(cgv2::k_count_final, dim3(1), dim3(cgv2::kDBlock), 0, stream, cpart, nbd, st.counters);
   }
   return hipGetLastError();
 }

@@ -174,10 +174,14 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
                                                     int V, int64_t HW, float lambda, float* __restrict__ loss) {
   __shared__ double red[2][256];
   for (int v = 0; v < V; ++v) {
+    // fixed summation order per thread; unrolled so that eight loads are in flight
     double a = 0, b = 0;
+    const double2* pv = (const double2*)partial + v * blocks_per_view;
+#pragma unroll 8
     for (int64_t k = threadIdx.x; k < blocks_per_view; k += 256) {
-      a += partial[2 * (v * blocks_per_view + k)];
-      b += partial[2 * (v * blocks_per_view + k) + 1];
+      const double2 q = pv[k];
+      a += q.x;
+      b += q.y;
     }
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = b;
@@ -212,7 +216,7 @@ size_t cgv2_loss_ws_layout(int W, int H, int V, size_t* off) {
 
 hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, int H, float lambda, float* d_img,
                             float* d_ssim, float* loss, void* ws, hipStream_t st) {
-  size_t off[2];
+  size_t off[kLossOffs];
   cgv2_loss_ws_layout(W, H, V, off);
   float* maps = (float*)((char*)ws + off[0]);
   double* partial = (double*)((char*)ws + off[1]);
