@@ -5,14 +5,16 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 (``paper_2411_00771_amd``) and never imports it; the two meet only in the
 seeded input generators.  Each wrapper names the paper passage it follows; the
 arithmetic lives in ``cgv2_oracle.cpp`` (projection, binning, Eq. 1 blending,
-its reverse mode, SSIM) and in :func:`densify_stats` below (Eq. 2 and the
-elongation rate of Sec. 3.2).
+its reverse mode, SSIM, the Eq. 3 contribution) and in :func:`densify_stats`,
+:func:`average_contribution` and :func:`trim_threshold` below (Eq. 2, the
+elongation rate of Sec. 3.2, Eq. 4 and the trimming bound of Sec. 3.3).
 
 Parity-unpinned readings (the paper fixes none of them; they are pinned to the
 mathematics instead): pixel-centre sampling, the screen low-pass filter width,
 the lossless opacity-aware cutoff, the intersection depth of the 3D branch, the
 median-depth rule, the SH offset/clamp, the per-view DGD averages, the
-elongation threshold and the 2DGS view-space gradient.
+elongation threshold, the 2DGS view-space gradient, the contribution region
+(the pixels where a surfel is blended) and the percentile bound of the trim.
 """
 from __future__ import annotations
 
@@ -169,6 +171,45 @@ def render_bwd(proj, cam, offsets, ids, d_rgb=None, d_depth=None, d_depth_med=No
                          None if tile_mask is None else _p(np.ascontiguousarray(tile_mask, np.uint8)))
     g["n_pairs"] = int(counters[0])
     return g
+
+
+def contribution(proj, cam, offsets, ids, gamma=0.5, fragile=-1.0):
+    """Per-surfel contribution in one view, Sec. 3.3 Eq. 3: C = (1/|P|) sum_P alpha^gamma T^(1-gamma) over
+    the pixels P where the surfel is blended (T = transmittance in front of it); C = 0 when P is empty.
+    'fragile' marks surfels evaluated at a pixel whose decision margin is below the given bound."""
+    n = proj["M"].shape[0]
+    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64), fragile=np.zeros(n, np.uint8))
+    lib().orc_contribution(ctypes.c_int64(n), _p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]),
+                           _p(proj["opacity"]), _p(_d(cam.as_array())), _p(np.ascontiguousarray(offsets, np.int64)),
+                           _p(np.ascontiguousarray(ids, np.int32)), ctypes.c_double(gamma), ctypes.c_double(fragile),
+                           _p(out["sum"]), _p(out["cnt"]), _p(out["fragile"]))
+    out["C"] = np.where(out["cnt"] > 0, out["sum"] / np.maximum(out["cnt"], 1), 0.0)
+    return out
+
+
+def contribution_brute(proj, cam, gamma=0.5):
+    """Eq. 3 with every surviving surfel blended at every pixel (no tiles)."""
+    n = proj["M"].shape[0]
+    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64))
+    lib().orc_contribution_brute(ctypes.c_int64(n), _p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]),
+                                 _p(proj["opacity"]), _p(np.ascontiguousarray(proj["flags"], np.int32)),
+                                 _p(_d(cam.as_array())), ctypes.c_double(gamma), _p(out["sum"]), _p(out["cnt"]))
+    out["C"] = np.where(out["cnt"] > 0, out["sum"] / np.maximum(out["cnt"], 1), 0.0)
+    return out
+
+
+def average_contribution(per_view):
+    """Eq. 4: the mean of the single-view contributions over the views of the block."""
+    return np.mean(np.stack([np.asarray(c, np.float64) for c in per_view]), axis=0)
+
+
+def trim_threshold(C, ratio):
+    """Sec. 3.3 trimming: the bound is the floor(ratio (n - 1))-th smallest contribution (0-based; the
+    'lower' percentile); every surfel at or below it is removed.  Returns (bound, mask)."""
+    C = np.asarray(C)
+    k = int(np.floor(ratio * (C.size - 1)))
+    bound = np.sort(C, kind="stable")[k]
+    return bound, C <= bound
 
 
 def project_bwd(scene, cam, g):

@@ -15,6 +15,8 @@
 //   orc_render_brute the same blend over *all* surviving surfels (no tiling): pins the lists
 //   orc_render_bwd   reverse-mode of orc_render over stored fragments (chain rule, no T division)
 //   orc_project_bwd  chain from d(M, colour, normal, opacity) to the parameters
+//   orc_contribution per-surfel contribution of one view (Sec. 3.3, Eq. 3) over the blended pixels;
+//                    orc_contribution_brute the same over every surviving surfel (pins the tiled pass)
 //   orc_ssim_loss    (1-l) L1 + l (1 - SSIM) with an 11x11 Gaussian window (Sec. 3.1) and its gradient,
 //                    once in total and once for the SSIM term alone (the DGD source of Eq. 2)
 //   orc_sh_eval      real spherical harmonics from the associated-Legendre definition
@@ -324,9 +326,15 @@ struct PixOut {
 
 // One pixel's front-to-back blend over an ordered list of surfel indices.  'order[e]' gives
 // the surfel of list entry e; entries [start, end).
-template <class IdOf>
+// on_frag(n, alpha, T) is called for every contributing fragment with the transmittance in front of it.
+struct NoFrag {
+  void operator()(int64_t, double, double) const {}
+};
+
+template <class IdOf, class OnFrag = NoFrag>
 void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const double* rgb,
-                 const double* nrm, const double* opac, const Cam& cam, double x, double y, PixOut& o) {
+                 const double* nrm, const double* opac, const Cam& cam, double x, double y, PixOut& o,
+                 OnFrag on_frag = OnFrag()) {
   double T = 1, C[3] = {0, 0, 0}, D = 0, N[3] = {0, 0, 0}, Dmed = 0;
   int64_t med = -1, last = start, n_eval = 0, n_con = 0;
   double margin = INFINITY;
@@ -354,6 +362,7 @@ void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const 
     margin = std::min(margin, relmargin(T, 0.5) - dT);
     dT = dTn;
     mix((uint64_t)n * 4 + (e.is3d ? 1 : 0) + (e.clamped ? 2 : 0));
+    on_frag(n, e.alpha, T);
     const double w = e.alpha * T;
     for (int c = 0; c < 3; ++c) { C[c] += w * rgb[3 * n + c]; N[c] += w * nrm[3 * n + c]; }
     D += w * e.zf;
@@ -377,6 +386,30 @@ void store_pix(const PixOut& po, int64_t p, int64_t HW, double* out_rgb, double*
   out_last[p] = po.last; out_med[p] = po.med;
   if (out_margin) out_margin[p] = po.margin;
   if (out_sig) out_sig[p] = po.sig;
+}
+
+template <class Range>
+void contribution_pass(Range range, const double* M, const double* rgb, const double* nrm, const double* opac,
+                       const Cam& cam, double gamma, double fragile_thr, double* out_sum, int64_t* out_cnt,
+                       uint8_t* out_fragile) {
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j < cam.H; ++j) {
+    for (int i = 0; i < cam.W; ++i) {
+      int64_t start, end;
+      auto id_of = range(i, j, start, end);
+      PixOut po;
+      blend_pixel(id_of, start, end, M, rgb, nrm, opac, cam, i + 0.5, j + 0.5, po,
+                  [&](int64_t n, double alpha, double T) {
+                    const double c = std::pow(alpha, gamma) * std::pow(T, 1 - gamma);
+#pragma omp atomic
+                    out_sum[n] += c;
+#pragma omp atomic
+                    out_cnt[n] += 1;
+                  });
+      if (po.margin < fragile_thr)
+        for (int64_t k = start; k < start + po.n_eval; ++k) out_fragile[id_of(k)] = 1;
+    }
+  }
 }
 
 }  // namespace
@@ -583,6 +616,53 @@ int orc_render_brute(int64_t n, const double* M, const double* rgb, const double
       out_depth[p] = po.D; out_dmed[p] = po.Dmed; out_alpha[p] = po.A; out_T[p] = po.T;
       out_med_id[p] = po.med >= 0 ? order[po.med].second : -1;
     }
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Contribution of every surfel in one view (Sec. 3.3, Eq. 3): over the pixels P_k at which the surfel
+// is blended as a fragment, the sum of alpha^gamma T^(1 - gamma) with T the transmittance in front of
+// it, and |P_k|; C_{n,k} = sum / |P_k| (0 when P_k is empty).  fragile[n] = 1 when the surfel is
+// evaluated at a pixel whose smallest decision margin is below fragile_thr (there an FP32 evaluation
+// may decide differently).  Accumulates into out_sum / out_cnt / out_fragile (caller zeroes).
+// ------------------------------------------------------------------------------------------
+int orc_contribution(int64_t n, const double* M, const double* rgb, const double* nrm, const double* opac,
+                     const double* camv, const int64_t* offsets, const int32_t* ids, double gamma, double fragile_thr,
+                     double* out_sum, int64_t* out_cnt, uint8_t* out_fragile) {
+  (void)n;
+  const Cam cam = load_cam(camv);
+  const int tx = (cam.W + kTile - 1) / kTile;
+  contribution_pass(
+      [&](int i, int j, int64_t& start, int64_t& end) {
+        const int64_t t = (int64_t)(j / kTile) * tx + i / kTile;
+        start = offsets[t];
+        end = offsets[t + 1];
+        return [ids](int64_t k) { return (int64_t)ids[k]; };
+      },
+      M, rgb, nrm, opac, cam, gamma, fragile_thr, out_sum, out_cnt, out_fragile);
+  return 0;
+}
+
+// The same over every surviving surfel per pixel (no tiles): pins the tiled pass.
+int orc_contribution_brute(int64_t n, const double* M, const double* rgb, const double* nrm, const double* opac,
+                           const int32_t* flags, const double* camv, double gamma, double* out_sum,
+                           int64_t* out_cnt) {
+  const Cam cam = load_cam(camv);
+  std::vector<std::pair<uint64_t, int64_t>> order;
+  for (int64_t i = 0; i < n; ++i) {
+    if (flags[i] & (F_NEAR | F_OPACITY | F_BEHIND | F_NONFINITE)) continue;
+    order.push_back({((uint64_t)f32bits(M[9 * i + 8]) << 32) | (uint32_t)i, i});
+  }
+  std::sort(order.begin(), order.end());
+  std::vector<uint8_t> fragile((size_t)std::max<int64_t>(n, 1), 0);
+  const std::vector<std::pair<uint64_t, int64_t>>* ord = &order;
+  contribution_pass(
+      [&](int, int, int64_t& start, int64_t& end) {
+        start = 0;
+        end = (int64_t)ord->size();
+        return [ord](int64_t k) { return (*ord)[k].second; };
+      },
+      M, rgb, nrm, opac, cam, gamma, -1.0, out_sum, out_cnt, fragile.data());
   return 0;
 }
 

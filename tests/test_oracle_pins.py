@@ -13,6 +13,9 @@ P9  analytic gradients == FP64 central differences
 P10 view-space gradient == derivative w.r.t. a rigid screen translation of M
 P11 DGD (Eq. 2) hand example, clamp at 1, invariance to invisible surfels; elongation rate
 P12 SSIM identities, constant-image closed form, finite differences of the loss
+P13 contribution (Eq. 3): closed forms for one facing surfel and for two stacked facing surfels;
+    tiled == brute force; sum of |P| == the render's contributing pairs
+P14 Eq. 4 average and the trimming bound on hand-worked arrays
 """
 import math
 
@@ -363,3 +366,87 @@ def test_p12_ssim_identities_closed_form_and_fd():
         assert abs((lp["loss"] - lm["loss"]) / (2 * eps) - lo["d_total"][idx]) < 1e-8
         s_fd = 0.2 * ((1 - lp["ssim"]) - (1 - lm["ssim"])) / (2 * eps)
         assert abs(s_fd - lo["d_ssim"][idx]) < 1e-8
+
+
+# ---- P13 / P14: contribution-based trimming (Sec. 3.3, Eq. 3 and Eq. 4) ---------------------------
+
+def _contrib(P, cam, gamma):
+    proj = oracle.project(P, cam)
+    off, ids = oracle.bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height)
+    return proj, off, ids, oracle.contribution(proj, cam, off, ids, gamma)
+
+
+def _facing_alpha(cam, z, scale, o):
+    """alpha of a camera-facing isotropic surfel on the optical axis at depth z, per pixel sample."""
+    i = np.arange(cam.width)[None, :] + 0.5
+    j = np.arange(cam.height)[:, None] + 0.5
+    X = (i - f32(cam.cx)) * z / f32(cam.fx)
+    Y = (j - f32(cam.cy)) * z / f32(cam.fy)
+    return np.minimum(0.99, o * np.exp(-(X ** 2 + Y ** 2) / (2 * scale ** 2)))
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.25])
+def test_p13_contribution_single_facing_surfel(gamma):
+    cam = scenes.tiny_camera()
+    logit = 1.3
+    o = 1 / (1 + math.exp(-logit))
+    P = one_surfel_scene([(0.0, 0.0, 0.0)], 0.3, logit)
+    _, _, _, c = _contrib(P, cam, gamma)
+    a = _facing_alpha(cam, 3.0, 0.3, o)
+    region = a >= 1 / 255
+    assert c["cnt"][0] == region.sum()
+    # nothing lies in front: T = 1 at every pixel of the region
+    assert abs(c["C"][0] - np.mean(a[region] ** gamma)) < 1e-12
+
+
+def test_p13_contribution_two_stacked_surfels():
+    cam = scenes.tiny_camera()
+    gamma = 0.5
+    o = 0.9
+    logit = math.log(o / (1 - o))
+    # front surfel at depth 2, back surfel at depth 2.5, both on the optical axis and facing the camera
+    P = one_surfel_scene([(0.0, 0.0, -1.0), (0.0, 0.0, -0.5)], 0.3, logit)
+    _, _, _, c = _contrib(P, cam, gamma)
+    af = _facing_alpha(cam, 2.0, 0.3, o)
+    ab = _facing_alpha(cam, 2.5, 0.3, o)
+    front, back = af >= 1 / 255, ab >= 1 / 255
+    T_back = np.where(front, 1 - af, 1.0)  # transmittance in front of the back surfel
+    assert c["cnt"][0] == front.sum() and c["cnt"][1] == back.sum()
+    assert abs(c["C"][0] - np.mean(af[front] ** gamma)) < 1e-12
+    expect = np.mean(ab[back] ** gamma * T_back[back] ** (1 - gamma))
+    assert abs(c["C"][1] - expect) < 1e-12
+
+
+def test_p13_contribution_tiled_equals_brute_and_counts():
+    w = scenes.workload(0)
+    sc, cam = w["scene"], w["cameras"][0]
+    proj = oracle.project(sc, cam)
+    off, ids = oracle.bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height)
+    for gamma in (0.5, 0.0, 1.0):
+        t = oracle.contribution(proj, cam, off, ids, gamma)
+        b = oracle.contribution_brute(proj, cam, gamma)
+        assert np.array_equal(t["cnt"], b["cnt"])
+        assert np.abs(t["sum"] - b["sum"]).max() <= 1e-12 * max(1.0, np.abs(b["sum"]).max())
+    img = oracle.render(proj, cam, off, ids)
+    assert t["cnt"].sum() == img["n_con"]
+    # gamma = 0: the mean transmittance in front, within (0, 1]; gamma = 1: the mean alpha, within [1/255, 0.99]
+    t0 = oracle.contribution(proj, cam, off, ids, 0.0)
+    seen = t0["cnt"] > 0
+    assert np.all(t0["C"][seen] <= 1) and np.all(t0["C"][seen] > 0)
+    t1 = oracle.contribution(proj, cam, off, ids, 1.0)
+    assert np.all(t1["C"][seen] >= 1 / 255 - 1e-15) and np.all(t1["C"][seen] <= 0.99 + 1e-15)
+    assert np.all(t0["C"][~seen] == 0)
+
+
+def test_p14_average_and_trim_bound():
+    assert np.array_equal(oracle.average_contribution([[0, 1, 2], [2, 1, 0]]), [1.0, 1.0, 1.0])
+    C = np.array([0.3, 0.0, 0.1, 0.0, 0.5, 0.2, 0.4, 0.1, 0.6, 0.05])
+    # ratio .25 on 10 values: index floor(.25 * 9) = 2 of [0, 0, .05, .1, .1, .2, .3, .4, .5, .6]
+    bound, mask = oracle.trim_threshold(C, 0.25)
+    assert bound == 0.05 and list(np.flatnonzero(mask)) == [1, 3, 9]
+    bound, mask = oracle.trim_threshold(C, 0.1)   # index 0: the never-seen surfels only
+    assert bound == 0.0 and list(np.flatnonzero(mask)) == [1, 3]
+    bound, mask = oracle.trim_threshold(C, 0.4)   # index 3; ties at the bound are removed too
+    assert bound == 0.1 and list(np.flatnonzero(mask)) == [1, 2, 3, 7, 9]
+    bound, mask = oracle.trim_threshold(C, 1.0)
+    assert bound == 0.6 and mask.all()
