@@ -32,6 +32,8 @@ PEAK_HBM_GBS = 8000.0
 # pair; reverse 42 per walked pair + 150 per contributing pair
 F_FWD_EVAL, F_FWD_CON = 36, 26
 F_BWD_WALK, F_BWD_CON = 42, 150
+# contribution pass (Eq. 3): the evaluation, then T update and alpha^gamma T^(1-gamma) per contributing pair
+F_CON_EVAL, F_CON_CON = 36, 12
 
 
 def log(msg):
@@ -60,6 +62,41 @@ def cpu_baseline(scene, cam, target):
     return dict(value=1.0 / dt, unit="iters/s", cores=cores, kind="oracle",
                 sample=f"one full 1600x1066 view of the 1M-surfel scene (fwd+loss+bwd, both view-space "
                        f"gradients, densify), {dt:.1f} s")
+
+
+def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=2):
+    """Trimming pass of Sec. 3.3 over every view of the block: per-view contribution (Eq. 3) into a
+    running sum, the average of Eq. 4, and the percentile mask.  Only the contribution calls and the
+    trim are timed (the per-view project + bin_sort that provide the bins are not)."""
+    import torch
+    from paper_2411_00771_amd import raster
+    n = eng.n
+    c_sum = torch.zeros(n, device="cuda:0")
+    times, flops = [], 0.0
+    for rep in range(reps):
+        c_sum.zero_()
+        for k, c in enumerate(cams):
+            eng.project(params, c)
+            eng.bin_sort(c)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            eng.contribution(c, gamma, c_sum=c_sum)
+            e1.record()
+            times.append((rep, e0, e1))
+            if rep == reps - 1:
+                flops += F_CON_EVAL * counts[k][0] + F_CON_CON * counts[k][1]
+    c_avg = c_sum / len(cams)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    bound, mask, removed = raster.trim_mask(c_avg, ratio)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for r, a, b in times if r == reps - 1]
+    per_view = float(np.mean(ms))
+    return {"views": len(cams), "gamma": gamma, "ratio": ratio, "ms_per_view": round(per_view, 4),
+            "views_per_s": round(1e3 / per_view, 2),
+            "tflops": round(flops / (sum(ms) * 1e-3) / 1e12, 3),
+            "trim_ms": round(t0.elapsed_time(t1), 4), "removed": int(removed.item()), "bound": float(bound.item())}
 
 
 def bench_batched(steps, warmup, n=None):
@@ -184,6 +221,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-contribution", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -332,6 +370,9 @@ def main():
         "intersections_max": int(need),
         "roofline": roof,
     }
+    if not args.no_contribution:
+        out["contribution"] = bench_contribution(eng, params, cams, counts)
+        log(f"[bench] contribution/trim: {out['contribution']}")
     target0 = targets[0][0].cpu().numpy().astype(np.float64)
     del eng, grads, state, params, targets
     torch.cuda.empty_cache()

@@ -255,6 +255,32 @@ int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_
 int cgv2_render_count(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V,
                       int64_t n, uint64_t* counters, void* hip_stream);
 
+/* Workspace bytes for cgv2_contribution. */
+size_t cgv2_contribution_workspace(int64_t n, int32_t V);
+
+/* Contribution of each surfel (Sec. 3.3, Eq. 3) in each of the V views of the call: over the pixels P at
+ * which the surfel is blended (the decisions of cgv2_render_fwd), C = (1/|P|) sum alpha^gamma
+ * T^(1-gamma) with T the transmittance in front of it; C = 0 when P is empty.  Any output may be NULL:
+ *   c_view [V][n] receives C per view;
+ *   c_sum  [n]    accumulates (+=) the sum of C over the V views (Eq. 4 averages over the block's views:
+ *                 divide by their number; the caller zeroes it);
+ *   pixels [V][n] receives |P| (u32).
+ * proj, bins, cams, V and n as for cgv2_render_fwd (bins must be valid).
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_contribution(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                      float gamma, float* c_view, float* c_sum, uint32_t* pixels, void* workspace, size_t ws_bytes,
+                      void* hip_stream);
+
+/* Workspace bytes for cgv2_trim_mask. */
+size_t cgv2_trim_workspace(int64_t n);
+
+/* Trimming of Sec. 3.3: *bound (device) = the floor(ratio (n - 1))-th smallest of c[0 .. n) (0-based;
+ * c >= 0, found exactly by radix selection on the float bits), mask[i] = 1 when c[i] <= *bound, else
+ * 0, and *removed (device, u32) = the number of ones.  ratio in [0, 1], n >= 1.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_trim_mask(const float* c, int64_t n, float ratio, float* bound, uint8_t* mask, uint32_t* removed,
+                   void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* Error string for a CGV2_E* code; thread-local hipError_t of the last failing launch. */
 const char* cgv2_strerror(int code);
 int cgv2_last_hip_error(void);

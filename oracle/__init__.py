@@ -176,9 +176,10 @@ def render_bwd(proj, cam, offsets, ids, d_rgb=None, d_depth=None, d_depth_med=No
 def contribution(proj, cam, offsets, ids, gamma=0.5, fragile=-1.0):
     """Per-surfel contribution in one view, Sec. 3.3 Eq. 3: C = (1/|P|) sum_P alpha^gamma T^(1-gamma) over
     the pixels P where the surfel is blended (T = transmittance in front of it); C = 0 when P is empty.
-    'fragile' marks surfels evaluated at a pixel whose decision margin is below the given bound."""
+    'fragile' counts, per surfel, the pixels where it is evaluated and whose decision margin is below the
+    given bound (each can move its count by at most 1 and its sum by at most one term)."""
     n = proj["M"].shape[0]
-    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64), fragile=np.zeros(n, np.uint8))
+    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64), fragile=np.zeros(n, np.int32))
     lib().orc_contribution(ctypes.c_int64(n), _p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]),
                            _p(proj["opacity"]), _p(_d(cam.as_array())), _p(np.ascontiguousarray(offsets, np.int64)),
                            _p(np.ascontiguousarray(ids, np.int32)), ctypes.c_double(gamma), ctypes.c_double(fragile),

@@ -391,7 +391,7 @@ void store_pix(const PixOut& po, int64_t p, int64_t HW, double* out_rgb, double*
 template <class Range>
 void contribution_pass(Range range, const double* M, const double* rgb, const double* nrm, const double* opac,
                        const Cam& cam, double gamma, double fragile_thr, double* out_sum, int64_t* out_cnt,
-                       uint8_t* out_fragile) {
+                       int32_t* out_fragile) {
 #pragma omp parallel for schedule(dynamic)
   for (int j = 0; j < cam.H; ++j) {
     for (int i = 0; i < cam.W; ++i) {
@@ -407,7 +407,10 @@ void contribution_pass(Range range, const double* M, const double* rgb, const do
                     out_cnt[n] += 1;
                   });
       if (po.margin < fragile_thr)
-        for (int64_t k = start; k < start + po.n_eval; ++k) out_fragile[id_of(k)] = 1;
+        for (int64_t k = start; k < start + po.n_eval; ++k) {
+#pragma omp atomic
+          out_fragile[id_of(k)] += 1;
+        }
     }
   }
 }
@@ -622,13 +625,14 @@ int orc_render_brute(int64_t n, const double* M, const double* rgb, const double
 // ------------------------------------------------------------------------------------------
 // Contribution of every surfel in one view (Sec. 3.3, Eq. 3): over the pixels P_k at which the surfel
 // is blended as a fragment, the sum of alpha^gamma T^(1 - gamma) with T the transmittance in front of
-// it, and |P_k|; C_{n,k} = sum / |P_k| (0 when P_k is empty).  fragile[n] = 1 when the surfel is
-// evaluated at a pixel whose smallest decision margin is below fragile_thr (there an FP32 evaluation
-// may decide differently).  Accumulates into out_sum / out_cnt / out_fragile (caller zeroes).
+// it, and |P_k|; C_{n,k} = sum / |P_k| (0 when P_k is empty).  fragile[n] counts the pixels at which
+// the surfel is evaluated and whose smallest decision margin is below fragile_thr (there an FP32
+// evaluation may decide differently, moving the surfel's count by at most 1 and its sum by at most one
+// term).  Accumulates into out_sum / out_cnt / out_fragile (caller zeroes).
 // ------------------------------------------------------------------------------------------
 int orc_contribution(int64_t n, const double* M, const double* rgb, const double* nrm, const double* opac,
                      const double* camv, const int64_t* offsets, const int32_t* ids, double gamma, double fragile_thr,
-                     double* out_sum, int64_t* out_cnt, uint8_t* out_fragile) {
+                     double* out_sum, int64_t* out_cnt, int32_t* out_fragile) {
   (void)n;
   const Cam cam = load_cam(camv);
   const int tx = (cam.W + kTile - 1) / kTile;
@@ -654,7 +658,7 @@ int orc_contribution_brute(int64_t n, const double* M, const double* rgb, const 
     order.push_back({((uint64_t)f32bits(M[9 * i + 8]) << 32) | (uint32_t)i, i});
   }
   std::sort(order.begin(), order.end());
-  std::vector<uint8_t> fragile((size_t)std::max<int64_t>(n, 1), 0);
+  std::vector<int32_t> fragile((size_t)std::max<int64_t>(n, 1), 0);
   const std::vector<std::pair<uint64_t, int64_t>>* ord = &order;
   contribution_pass(
       [&](int, int, int64_t& start, int64_t& end) {

@@ -19,7 +19,8 @@ F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16,
 EXPORTS = ["cgv2_project", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
            "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
            "cgv2_project_bwd", "cgv2_densify_workspace",
-           "cgv2_densify_stats", "cgv2_render_count", "cgv2_strerror", "cgv2_last_hip_error"]
+           "cgv2_densify_stats", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
+           "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_strerror", "cgv2_last_hip_error"]
 
 P = ctypes.c_void_p
 
@@ -106,6 +107,11 @@ def lib():
         "cgv2_densify_workspace": (sz, [i64, i32]),
         "cgv2_densify_stats": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Grads), i32,
                                               ctypes.POINTER(DensifyParams), ctypes.POINTER(DensifyState), P, sz, P]),
+        "cgv2_contribution_workspace": (sz, [i64, i32]),
+        "cgv2_contribution": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Bins), ctypes.POINTER(Camera), i32,
+                                             i64, ctypes.c_float, P, P, P, P, sz, P]),
+        "cgv2_trim_workspace": (sz, [i64]),
+        "cgv2_trim_mask": (ctypes.c_int, [P, i64, ctypes.c_float, P, P, P, P, sz, P]),
         "cgv2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cgv2_last_hip_error": (ctypes.c_int, []),
     }

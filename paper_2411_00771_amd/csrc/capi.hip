@@ -238,4 +238,44 @@ int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_
   return hip_status(cgv2_launch_densify(*s, *proj, *g, V, *prm, *st, workspace, (hipStream_t)stream));
 }
 
+size_t cgv2_contribution_workspace(int64_t n, int32_t V) {
+  if (n < 0 || V < 1) return 0;
+  return cgv2_contribution_ws_layout(n, V);
+}
+
+int cgv2_contribution(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_camera* cams, int32_t V, int64_t n,
+                      float gamma, float* c_view, float* c_sum, uint32_t* pixels, void* workspace, size_t ws_bytes,
+                      void* stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || n < 0 || !(gamma >= 0.f && gamma <= 1.f))
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_contribution_workspace(n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (n == 0) return CGV2_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  const int tx = tiles_x(cams), ty = tiles_y(cams);
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const cgv2::CamPack cp = pack(cams, v0, cnt);
+    int rc = hip_status(cgv2_launch_contribution_final(*proj, cp, n, V, workspace, true, nullptr, nullptr, nullptr, st));
+    if (rc) return rc;
+    rc = hip_status(cgv2_launch_contribution(*proj, *bins, cp, n, tx, ty, gamma, (float*)workspace, st));
+    if (rc) return rc;
+  }
+  return hip_status(cgv2_launch_contribution_final(*proj, pack(cams, 0, V < cgv2::kMaxViews ? V : cgv2::kMaxViews), n,
+                                                   V, workspace, false, c_view, c_sum, pixels, st));
+}
+
+size_t cgv2_trim_workspace(int64_t n) {
+  if (n < 1) return 0;
+  size_t off[kTrimOffs];
+  return cgv2_trim_ws_layout(n, off);
+}
+
+int cgv2_trim_mask(const float* c, int64_t n, float ratio, float* bound, uint8_t* mask, uint32_t* removed,
+                   void* workspace, size_t ws_bytes, void* stream) {
+  if (!c || !mask || n < 1 || !(ratio >= 0.f && ratio <= 1.f) || n > 0xffffffffLL) return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_trim_workspace(n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  const uint32_t k = (uint32_t)floor((double)ratio * (double)(n - 1));
+  return hip_status(cgv2_launch_trim(c, n, k, bound, mask, removed, workspace, (hipStream_t)stream));
+}
+
 }  // extern "C"

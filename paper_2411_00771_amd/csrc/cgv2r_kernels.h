@@ -12,7 +12,7 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
 // Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
-constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2;
+constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3;
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
@@ -34,3 +34,15 @@ size_t cgv2_densify_ws_layout(int64_t n, int V, size_t* off);
 hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const cgv2_grads& g, int V,
                                const cgv2_densify_params& prm, const cgv2_densify_state& st, void* ws,
                                hipStream_t stream);
+
+// contribution-based trimming (render.hip: the traversal; trim.hip: the rest)
+hipError_t cgv2_launch_contribution(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
+                                    int tiles_x, int tiles_y, float gamma, float* cws, hipStream_t st);
+size_t cgv2_contribution_ws_layout(int64_t n, int V);
+// zero = true: clear the pairs of the chunk's visible surfels; false: finalise every view of the call
+hipError_t cgv2_launch_contribution_final(const cgv2_proj& p, const cgv2::CamPack& cams, int64_t n, int V_total,
+                                          void* ws, bool zero, float* c_view, float* c_sum, uint32_t* pixels,
+                                          hipStream_t st);
+size_t cgv2_trim_ws_layout(int64_t n, size_t* off);
+hipError_t cgv2_launch_trim(const float* c, int64_t n, uint32_t k, float* bound, uint8_t* mask, uint32_t* removed,
+                            void* ws, hipStream_t st);

@@ -35,6 +35,8 @@ struct RenderArgs {
   int tiles_x, tiles_y, tiles;
   cgv2_image img;
   unsigned long long* counters;
+  float* cws;   // contribution mode: [V][n] pairs (sum of alpha^gamma T^(1-gamma), pixel count)
+  float gamma;
 };
 
 // LDS record, five float4 and the quadrant mask:
@@ -97,7 +99,7 @@ __device__ __forceinline__ void lane_terms(float lx0, float ly0, const float4& q
 // both take bit-identical decisions.  rho is half the Mahalanobis-type distance:
 // rho = min(rho_3d, rho_2d) / 2, alpha_raw = o exp(-rho).
 struct Px {
-  float xr, yr, P1, P2, w, iw, rho, araw, alpha;
+  float xr, yr, P1, P2, w, iw, rho, arg, araw, alpha;
   bool is3d;
 };
 
@@ -126,7 +128,8 @@ __device__ __forceinline__ void eval_px(const LaneTerms& t, float lo, Px& e) {
   const float r3 = nn * (e.iw * e.iw);
   e.is3d = r3 <= r2;
   e.rho = e.is3d ? r3 : r2;
-  e.araw = __builtin_amdgcn_exp2f(fmaf(e.rho, -kLog2e, lo));
+  e.arg = fmaf(e.rho, -kLog2e, lo);  // log2(alpha_raw)
+  e.araw = __builtin_amdgcn_exp2f(e.arg);
   e.alpha = fminf(kAlphaMax, e.araw);
 }
 
@@ -140,9 +143,13 @@ struct FwdState {
 
 // Returns false when no pixel of the quadrant takes the entry (wave-uniform); true otherwise, which
 // covers every entry with a contributing fragment (a superset is all the reverse pass needs).
-template <int k>
+// kContrib: also add the fragment's alpha^gamma T^(1-gamma) (T in front of it) and 1 to csum / ccnt.
+constexpr float kLog2AlphaMax = -0.014499569695115089f;  // log2(0.99)
+
+template <int k, bool kContrib>
 __device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, const float4& q3, const float4& q4,
-                                       uint32_t e_idx, FwdState& f, unsigned long long& n_con) {
+                                       uint32_t e_idx, FwdState& f, unsigned long long& n_con, float gamma,
+                                       float& csum, float& ccnt) {
   Px e;
   eval_px<k>(lt, q2.y, e);
   // wave-uniform skip when no pixel of the quadrant takes this surfel; otherwise branch-free: a
@@ -155,6 +162,13 @@ __device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, co
   f.done = f.done || stop;
   const bool upd = take && !stop;
   n_con += upd ? 1u : 0u;
+  if (kContrib) {
+    // log2(alpha) = min(log2(alpha_raw), log2(0.99))
+    const float la = fminf(e.arg, kLog2AlphaMax);
+    const float c = __builtin_amdgcn_exp2f(fmaf(gamma, la, (1.f - gamma) * __builtin_amdgcn_logf(f.T)));
+    csum += upd ? c : 0.f;
+    ccnt += upd ? 1.f : 0.f;
+  }
   const float wgt = upd ? a * f.T : 0.f;
   const float zf = e.is3d ? q2.w * e.iw : q2.z;
   f.C[0] = fmaf(wgt, q3.x, f.C[0]);
@@ -183,7 +197,9 @@ __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
 // kCount: instead of images, count the (pixel, list entry) pairs of the method (every entry a running
 // pixel meets, quadrant mask or not), the contributing pairs, and the pairs the reverse walks.
 // kMask: also write the per-entry quadrant mask img.qmask for the reverse pass.
-template <bool kCount, bool kMask>
+// kContrib: instead of images, add each surfel's contribution sums (Sec. 3.3, Eq. 3) of this view into
+// a.cws, one wave reduction and one atomic pair per (surfel, tile).
+template <bool kCount, bool kMask, bool kContrib>
 __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   __shared__ Stage s;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -237,10 +253,32 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         lane_terms(lx0, ly0, q0, q1, q2, lt);
         const uint32_t e_idx = base + (uint32_t)j;
         const uint64_t bit = 1ull << j;
-        if ((m & 1u) && fwd_px<0>(lt, q2, q3, q4, e_idx, f[0], n_con) && kMask) cq0 |= bit;
-        if ((m & 2u) && fwd_px<1>(lt, q2, q3, q4, e_idx, f[1], n_con) && kMask) cq1 |= bit;
-        if ((m & 4u) && fwd_px<2>(lt, q2, q3, q4, e_idx, f[2], n_con) && kMask) cq2 |= bit;
-        if ((m & 8u) && fwd_px<3>(lt, q2, q3, q4, e_idx, f[3], n_con) && kMask) cq3 |= bit;
+        float csum = 0.f, ccnt = 0.f;
+        bool took = false;
+        if ((m & 1u) && fwd_px<0, kContrib>(lt, q2, q3, q4, e_idx, f[0], n_con, a.gamma, csum, ccnt)) {
+          took = true;
+          if (kMask) cq0 |= bit;
+        }
+        if ((m & 2u) && fwd_px<1, kContrib>(lt, q2, q3, q4, e_idx, f[1], n_con, a.gamma, csum, ccnt)) {
+          took = true;
+          if (kMask) cq1 |= bit;
+        }
+        if ((m & 4u) && fwd_px<2, kContrib>(lt, q2, q3, q4, e_idx, f[2], n_con, a.gamma, csum, ccnt)) {
+          took = true;
+          if (kMask) cq2 |= bit;
+        }
+        if ((m & 8u) && fwd_px<3, kContrib>(lt, q2, q3, q4, e_idx, f[3], n_con, a.gamma, csum, ccnt)) {
+          took = true;
+          if (kMask) cq3 |= bit;
+        }
+        if (kContrib && took) {
+          const float ts = wave_sum_lane63(csum), tc = wave_sum_lane63(ccnt);
+          if (lane == 63 && tc > 0.f) {
+            float* w = a.cws + 2 * (vn + (int64_t)__float_as_uint(q3.w));
+            atomicAdd(w, ts);
+            atomicAdd(w + 1, tc);
+          }
+        }
       }
       if ((j & 15) == 15) {
         qlive = live_quadrants(f);
@@ -257,6 +295,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     qlive = live_quadrants(f);
     __syncthreads();
   }
+  if (kContrib) return;
   if (kCount) {
     unsigned long long n_bwd = 0;
 #pragma unroll
@@ -541,6 +580,8 @@ static cgv2::RenderArgs make_args(const cgv2_proj& p, const cgv2_bins& b, const 
   a.tiles = tiles_x * tiles_y;
   if (img) a.img = *img; else a.img = cgv2_image{};
   a.counters = counters;
+  a.cws = nullptr;
+  a.gamma = 0.f;
   return a;
 }
 
@@ -548,8 +589,8 @@ hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const 
                                   int tiles_x, int tiles_y, const cgv2_image& img, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
   const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
-  if (img.qmask) hipLaunchKernelGGL((cgv2::k_render_fwd<false, true>), dim3(grid), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL((cgv2::k_render_fwd<false, false>), dim3(grid), dim3(64), 0, st, a);
+  if (img.qmask) hipLaunchKernelGGL((cgv2::k_render_fwd<false, true, false>), dim3(grid), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -557,7 +598,7 @@ hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, cons
                                     int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, counters);
   const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
-  hipLaunchKernelGGL((cgv2::k_render_fwd<true, false>), dim3(grid), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((cgv2::k_render_fwd<true, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -577,5 +618,15 @@ hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const 
   const bool geom = up.d_depth || up.d_depth_med || up.d_normal || up.d_alpha;
   if (geom) hipLaunchKernelGGL(cgv2::k_render_bwd<true>, dim3(grid), dim3(64), 0, st, A);
   else hipLaunchKernelGGL(cgv2::k_render_bwd<false>, dim3(grid), dim3(64), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t cgv2_launch_contribution(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
+                                    int tiles_x, int tiles_y, float gamma, float* cws, hipStream_t st) {
+  cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, nullptr);
+  a.cws = cws;
+  a.gamma = gamma;
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
+  hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, true>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }

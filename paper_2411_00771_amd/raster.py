@@ -256,6 +256,18 @@ class Engine:
                                             ctypes.byref(state.struct()), ptr(self.ws_dens), self.ws_dens.numel(),
                                             _stream()), "cgv2_densify_stats")
 
+    # ---- contribution-based trimming (Sec. 3.3) --------------------------------------------------
+    def contribution(self, cams, gamma: float = 0.5, c_view=None, c_sum=None, pixels=None):
+        """Eq. 3 for the engine's V views from the current bins: c_view [V][n] (C per view), c_sum [n]
+        (+= sum over the V views), pixels [V][n] (|P|, int32 storage of u32); any may be None."""
+        L = _lib.lib()
+        need = L.cgv2_contribution_workspace(self.n, self.V)
+        if getattr(self, "ws_contrib", None) is None or self.ws_contrib.numel() < need:
+            self.ws_contrib = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        check(L.cgv2_contribution(ctypes.byref(self._proj), ctypes.byref(self._bins), cams, self.V, self.n,
+                                  float(gamma), ptr(c_view), ptr(c_sum), ptr(pixels), ptr(self.ws_contrib),
+                                  self.ws_contrib.numel(), _stream()), "cgv2_contribution")
+
     # ---- helpers -------------------------------------------------------------------------------
     def overflowed(self) -> bool:
         return bool(self.status.item() != 0)
@@ -275,6 +287,20 @@ class Engine:
         self.project(params, cams)
         self.bin_sort(cams)
         self.render(cams)
+
+
+def trim_mask(c, ratio: float):
+    """Sec. 3.3 trimming on a device array of contributions c [n] (float32, >= 0): returns
+    (bound [1], mask [n] uint8, removed [1] int32-stored u32), all on the device, stream-ordered."""
+    L = _lib.lib()
+    n = c.numel()
+    ws = torch.empty(max(L.cgv2_trim_workspace(n), 256), dtype=torch.uint8, device=c.device)
+    bound = torch.empty(1, dtype=torch.float32, device=c.device)
+    mask = torch.empty(n, dtype=torch.uint8, device=c.device)
+    removed = torch.empty(1, dtype=torch.int32, device=c.device)
+    check(L.cgv2_trim_mask(ptr(c), n, float(ratio), ptr(bound), ptr(mask), ptr(removed), ptr(ws), ws.numel(),
+                           _stream()), "cgv2_trim_mask")
+    return bound, mask, removed
 
 
 # ------------------------------------------------------------------------------------------------

@@ -96,6 +96,14 @@ def test_argument_validation_returns_einval():
                               ctypes.byref(g), None) == EINVAL
     assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), cams, 1, ctypes.c_void_p(256), 1 << 30, None,
                               None) == EINVAL
+    # contribution: bad gamma, missing bins; trim: bad ratio, n < 1, missing mask
+    ws = ctypes.c_void_p(256)
+    assert L.cgv2_contribution(ctypes.byref(p), ctypes.byref(okbins), cams, 1, 10, 1.5, None, None, None, ws,
+                               1 << 30, None) == EINVAL
+    assert L.cgv2_contribution(ctypes.byref(p), None, cams, 1, 10, 0.5, None, None, None, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_trim_mask(ws, 10, 1.5, None, ws, None, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_trim_mask(ws, 0, 0.1, None, ws, None, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_trim_mask(ws, 10, 0.1, None, None, None, ws, 1 << 30, None) == EINVAL
     prm = _lib.DensifyParams(0.9, 0.05, 2e-4)
     st = _lib.DensifyState()
     assert L.cgv2_densify_stats(ctypes.byref(s), ctypes.byref(p), ctypes.byref(g), 1, ctypes.byref(prm),
@@ -121,6 +129,10 @@ def test_small_workspace_returns_eworkspace():
     g = _lib.Grads(*[v] * 7)
     assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(cam), 1, v, ws - 1, ctypes.byref(g),
                               None) == _lib.CGV2_EWORKSPACE
+    assert L.cgv2_contribution(ctypes.byref(p), ctypes.byref(bins), ctypes.byref(cam), 1, 10, 0.5, None, None, None, v,
+                               L.cgv2_contribution_workspace(10, 1) - 1, None) == _lib.CGV2_EWORKSPACE
+    assert L.cgv2_trim_mask(v, 1000, 0.1, None, v, None, v, L.cgv2_trim_workspace(1000) - 1,
+                            None) == _lib.CGV2_EWORKSPACE
     assert L.cgv2_loss(v, v, 1, 64, 64, 0.2, v, v, v, v, L.cgv2_loss_workspace(64, 64, 1) - 1,
                        None) == _lib.CGV2_EWORKSPACE
 
