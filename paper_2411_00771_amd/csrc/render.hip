@@ -135,10 +135,11 @@ __device__ __forceinline__ void eval_px(const LaneTerms& t, float lo, Px& e) {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// T carries the pixel's state in its sign: T > 0 while the pixel runs (T >= 1e-4 then), -T once it has
+// stopped (or lies outside the image); the transmittance itself is |T|.
 struct FwdState {
   float T, C[3], D, Dm, N[3];
   uint32_t last, med;
-  bool done;
 };
 
 // Returns false when no pixel of the quadrant takes the entry (wave-uniform); true otherwise, which
@@ -146,20 +147,17 @@ struct FwdState {
 // kContrib: also add the fragment's alpha^gamma T^(1-gamma) (T in front of it) and 1 to csum / ccnt.
 constexpr float kLog2AlphaMax = -0.014499569695115089f;  // log2(0.99)
 
-template <int k, bool kContrib>
-__device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, const float4& q3, const float4& q4,
+template <bool kContrib>
+__device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const float4& q3, const float4& q4,
                                        uint32_t e_idx, FwdState& f, unsigned long long& n_con, float gamma,
                                        float& csum, float& ccnt) {
-  Px e;
-  eval_px<k>(lt, q2.y, e);
   // wave-uniform skip when no pixel of the quadrant takes this surfel; otherwise branch-free: a
   // contribution is a zero-weight no-op for pixels that skip or stop here
-  const bool take = !f.done && e.alpha >= kAlphaMin;
+  const bool take = f.T > 0.f && e.alpha >= kAlphaMin;
   if (__ballot(take) == 0) return false;
   const float a = take ? e.alpha : 0.f;
   const float Tn = f.T * (1.f - a);
   const bool stop = take && Tn < kTmin;
-  f.done = f.done || stop;
   const bool upd = take && !stop;
   n_con += upd ? 1u : 0u;
   if (kContrib) {
@@ -182,7 +180,7 @@ __device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, co
   f.Dm = m ? zf : f.Dm;
   f.med = m ? e_idx : f.med;
   f.last = upd ? e_idx + 1u : f.last;
-  f.T = upd ? Tn : f.T;
+  f.T = upd ? Tn : (stop ? -f.T : f.T);
   return true;
 }
 
@@ -190,7 +188,7 @@ __device__ __forceinline__ bool fwd_px(const LaneTerms& lt, const float4& q2, co
 __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
   uint32_t m = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) m |= (__ballot(!f[k].done) != 0 ? 1u : 0u) << k;
+  for (int k = 0; k < 4; ++k) m |= (__ballot(f[k].T > 0.f) != 0 ? 1u : 0u) << k;
   return m;
 }
 
@@ -221,8 +219,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-    f[k].done = !(px < W && py < H);
-    f[k].T = 1.f;
+    f[k].T = px < W && py < H ? 1.f : -1.f;
     f[k].D = 0.f;
     f[k].Dm = 0.f;
     f[k].last = start;
@@ -244,7 +241,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     for (int j = 0; j < cnt; ++j) {
       if (kCount) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) n_eval += f[k].done ? 0u : 1u;
+        for (int k = 0; k < 4; ++k) n_eval += f[k].T > 0.f ? 1u : 0u;
       }
       const uint32_t m = uniform(s.qm[j]) & qlive;
       if (m != 0) {
@@ -255,19 +252,24 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         const uint64_t bit = 1ull << j;
         float csum = 0.f, ccnt = 0.f;
         bool took = false;
-        if ((m & 1u) && fwd_px<0, kContrib>(lt, q2, q3, q4, e_idx, f[0], n_con, a.gamma, csum, ccnt)) {
+        Px e0, e1, e2, e3;
+        eval_px<0>(lt, q2.y, e0);
+        eval_px<1>(lt, q2.y, e1);
+        eval_px<2>(lt, q2.y, e2);
+        eval_px<3>(lt, q2.y, e3);
+        if ((m & 1u) && fwd_px<kContrib>(e0, q2, q3, q4, e_idx, f[0], n_con, a.gamma, csum, ccnt)) {
           took = true;
           if (kMask) cq0 |= bit;
         }
-        if ((m & 2u) && fwd_px<1, kContrib>(lt, q2, q3, q4, e_idx, f[1], n_con, a.gamma, csum, ccnt)) {
+        if ((m & 2u) && fwd_px<kContrib>(e1, q2, q3, q4, e_idx, f[1], n_con, a.gamma, csum, ccnt)) {
           took = true;
           if (kMask) cq1 |= bit;
         }
-        if ((m & 4u) && fwd_px<2, kContrib>(lt, q2, q3, q4, e_idx, f[2], n_con, a.gamma, csum, ccnt)) {
+        if ((m & 4u) && fwd_px<kContrib>(e2, q2, q3, q4, e_idx, f[2], n_con, a.gamma, csum, ccnt)) {
           took = true;
           if (kMask) cq2 |= bit;
         }
-        if ((m & 8u) && fwd_px<3, kContrib>(lt, q2, q3, q4, e_idx, f[3], n_con, a.gamma, csum, ccnt)) {
+        if ((m & 8u) && fwd_px<kContrib>(e3, q2, q3, q4, e_idx, f[3], n_con, a.gamma, csum, ccnt)) {
           took = true;
           if (kMask) cq3 |= bit;
         }
@@ -315,11 +317,12 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
     if (!(px < W && py < H)) continue;
     const int64_t p = (int64_t)py * W + px;
+    const float T = fabsf(f[k].T);
     if (im.rgb) {
       float* o = im.rgb + (int64_t)v * 3 * HW + p;
-      o[0] = fmaf(f[k].T, c.bg[0], f[k].C[0]);
-      o[HW] = fmaf(f[k].T, c.bg[1], f[k].C[1]);
-      o[2 * HW] = fmaf(f[k].T, c.bg[2], f[k].C[2]);
+      o[0] = fmaf(T, c.bg[0], f[k].C[0]);
+      o[HW] = fmaf(T, c.bg[1], f[k].C[1]);
+      o[2 * HW] = fmaf(T, c.bg[2], f[k].C[2]);
     }
     if (im.normal) {
       float* o = im.normal + (int64_t)v * 3 * HW + p;
@@ -330,8 +333,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     const int64_t vp = (int64_t)v * HW + p;
     if (im.depth) im.depth[vp] = f[k].D;
     if (im.depth_med) im.depth_med[vp] = f[k].Dm;
-    if (im.alpha) im.alpha[vp] = 1.f - f[k].T;
-    if (im.T_final) im.T_final[vp] = f[k].T;
+    if (im.alpha) im.alpha[vp] = 1.f - T;
+    if (im.T_final) im.T_final[vp] = T;
     if (im.last) im.last[vp] = f[k].last;
     if (im.med) im.med[vp] = f[k].med;
   }
