@@ -7,7 +7,8 @@ seeded input generators.  Each wrapper names the paper passage it follows; the
 arithmetic lives in ``cgv2_oracle.cpp`` (projection, binning, Eq. 1 blending,
 its reverse mode, SSIM, the Eq. 3 contribution) and in :func:`densify_stats`,
 :func:`average_contribution` and :func:`trim_threshold` below (Eq. 2, the
-elongation rate of Sec. 3.2, Eq. 4 and the trimming bound of Sec. 3.3).
+elongation rate of Sec. 3.2, Eq. 4 and the trimming bound of Sec. 3.3) and in
+:func:`densify_actions` / :func:`densify_apply` (the densification action).
 
 Parity-unpinned readings (the paper fixes none of them; they are pinned to the
 mathematics instead): pixel-centre sampling, the screen low-pass filter width,
@@ -211,6 +212,59 @@ def trim_threshold(C, ratio):
     k = int(np.floor(ratio * (C.size - 1)))
     bound = np.sort(C, kind="stable")[k]
     return bound, C <= bound
+
+
+def _rotation(q):
+    """Rotation matrices [n][3][3] of (unnormalised) quaternions q[4][n] = (w, x, y, z)."""
+    q = np.asarray(q, np.float64)
+    w, x, y, z = q / np.linalg.norm(q, axis=0)
+    return np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                     np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+                     np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+
+
+def densify_actions(cand, remove, log_scale, opacity_logit, dense_scale, min_opacity):
+    """Per-surfel action: 3 remove (trimmed, Sec. 3.3, or opacity below min_opacity), else for the
+    densification candidates of Sec. 3.2 (DGD high-gradient and not elongated) 1 clone when
+    max(s_u, s_v) <= dense_scale and 2 split otherwise, else 0 keep."""
+    s_max = np.exp(np.asarray(log_scale, np.float64)).max(axis=0)
+    o = 1 / (1 + np.exp(-np.asarray(opacity_logit, np.float64)))
+    act = np.where(np.asarray(cand, bool), np.where(s_max <= dense_scale, 1, 2), 0)
+    rm = np.asarray(remove, bool) if remove is not None else np.zeros(act.shape, bool)
+    return np.where(rm | (o < min_opacity), 3, act).astype(np.int32)
+
+
+def densify_apply(P, actions, z, shrink=1.6):
+    """The new surfel set: survivors (keep, clone) in id order, then for every clone (a copy) or split
+    (two children) in id order its new surfels.  Child c of a split surfel sits at
+    mu + R (s_u z[i, c, 0], s_v z[i, c, 1], 0) in its own plane and has its scales divided by 'shrink';
+    rotation, opacity and SH are copied.  P uses the generators' planar layout (sh [K][3][n])."""
+    act = np.asarray(actions)
+    R = _rotation(P["quat"])
+    s = np.exp(np.asarray(P["log_scale"], np.float64))
+    surv = np.flatnonzero((act == 0) | (act == 1))
+    out = {k: [] for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+
+    def take(idx, mean=None, log_scale=None):
+        out["mean"].append(np.asarray(P["mean"], np.float64)[:, idx] if mean is None else mean)
+        out["log_scale"].append(np.asarray(P["log_scale"], np.float64)[:, idx] if log_scale is None else log_scale)
+        out["quat"].append(np.asarray(P["quat"], np.float64)[:, idx])
+        out["opacity_logit"].append(np.asarray(P["opacity_logit"], np.float64)[idx])
+        out["sh"].append(np.asarray(P["sh"], np.float64)[:, :, idx])
+
+    take(surv)
+    for i in np.flatnonzero((act == 1) | (act == 2)):
+        if act[i] == 1:
+            take(np.array([i]))
+            continue
+        for c in range(2):
+            local = np.array([s[0, i] * z[i, c, 0], s[1, i] * z[i, c, 1], 0.0])
+            mu = np.asarray(P["mean"], np.float64)[:, i] + R[i] @ local
+            take(np.array([i]), mean=mu[:, None],
+                 log_scale=(np.asarray(P["log_scale"], np.float64)[:, i] - np.log(shrink))[:, None])
+    res = {k: np.concatenate(v, axis=-1) for k, v in out.items()}
+    res["sh_degree"] = P["sh_degree"]
+    return res
 
 
 def project_bwd(scene, cam, g):

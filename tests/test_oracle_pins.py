@@ -16,6 +16,8 @@ P12 SSIM identities, constant-image closed form, finite differences of the loss
 P13 contribution (Eq. 3): closed forms for one facing surfel and for two stacked facing surfels;
     tiled == brute force; sum of |P| == the render's contributing pairs
 P14 Eq. 4 average and the trimming bound on hand-worked arrays
+P15 densification action on a hand-worked six-surfel set: keep, clone, split (identity and quarter-turn
+    rotations), trimmed and low-opacity removal, output order and counts
 """
 import math
 
@@ -450,3 +452,45 @@ def test_p14_average_and_trim_bound():
     assert bound == 0.1 and list(np.flatnonzero(mask)) == [1, 2, 3, 7, 9]
     bound, mask = oracle.trim_threshold(C, 1.0)
     assert bound == 0.6 and mask.all()
+
+
+# ---- P15: densification action ---------------------------------------------------------------------
+
+def test_p15_densify_actions_and_apply_by_hand():
+    n = 6
+    mean = np.array([[0.0, 1.0, 2.0, 3.0, 4.0, 5.0],
+                     [0.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+                     [1.0, 1.0, 1.0, 1.0, 1.0, 1.0]])
+    su = np.array([0.01, 0.01, 0.2, 0.2, 0.01, 0.3])
+    sv = np.array([0.01, 0.005, 0.1, 0.2, 0.01, 0.1])
+    log_scale = np.log(np.stack([su, sv]))
+    c45 = math.cos(math.pi / 4)
+    quat = np.array([[1, 1, 1, 1, 1, c45], [0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, c45]], np.float64)
+    logit = np.array([2.0, 2.0, 2.0, 2.0, -6.0, 2.0])   # surfel 4: opacity 0.0025
+    sh = np.arange(16 * 3 * n, dtype=np.float64).reshape(16, 3, n)
+    P = dict(mean=mean, log_scale=log_scale, quat=quat, opacity_logit=logit, sh=sh, sh_degree=3)
+    cand = np.array([0, 1, 1, 1, 1, 1], bool)
+    remove = np.array([0, 0, 0, 1, 0, 0], bool)
+    act = oracle.densify_actions(cand, remove, log_scale, logit, dense_scale=0.05, min_opacity=0.005)
+    assert list(act) == [0, 1, 2, 3, 3, 2]
+    z = np.zeros((n, 2, 2))
+    z[2] = [[1.0, -2.0], [0.5, 0.25]]
+    z[5] = [[1.0, 0.0], [0.0, 1.0]]
+    out = oracle.densify_apply(P, act, z)
+    # survivors 0, 1; then the copy of 1, the children of 2, the children of 5
+    src = [0, 1, 1, 2, 2, 5, 5]
+    assert out["mean"].shape == (3, 7) and out["sh"].shape == (16, 3, 7)
+    assert np.array_equal(out["sh"], sh[:, :, src])
+    assert np.array_equal(out["quat"], quat[:, src]) and np.array_equal(out["opacity_logit"], logit[src])
+    # identity rotation: children at mu + (s_u z0, s_v z1, 0), scales / 1.6
+    assert np.allclose(out["mean"][:, 3], [2 + 0.2 * 1.0, 0.1 * -2.0, 1.0], atol=1e-15)
+    assert np.allclose(out["mean"][:, 4], [2 + 0.2 * 0.5, 0.1 * 0.25, 1.0], atol=1e-15)
+    assert np.allclose(out["log_scale"][:, 3], np.log([0.2 / 1.6, 0.1 / 1.6]), atol=1e-15)
+    # a quarter turn about the normal maps the tangent u onto +y and v onto -x
+    assert np.allclose(out["mean"][:, 5], [5.0, 0.3, 1.0], atol=1e-15)
+    assert np.allclose(out["mean"][:, 6], [5.0 - 0.1, 0.0, 1.0], atol=1e-15)
+    # survivors and clones are unchanged copies
+    assert np.array_equal(out["mean"][:, :3], mean[:, [0, 1, 1]])
+    assert np.array_equal(out["log_scale"][:, :3], log_scale[:, [0, 1, 1]])
+    keep, clone, split = (act == 0).sum(), (act == 1).sum(), (act == 2).sum()
+    assert out["mean"].shape[1] == keep + 2 * clone + 2 * split
