@@ -64,10 +64,11 @@ def cpu_baseline(scene, cam, target):
                        f"gradients, densify), {dt:.1f} s")
 
 
-def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=2):
+def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=3):
     """Trimming pass of Sec. 3.3 over every view of the block: per-view contribution (Eq. 3) into a
     running sum, the average of Eq. 4, and the percentile mask.  Only the contribution calls and the
-    trim are timed (the per-view project + bin_sort that provide the bins are not)."""
+    trim are timed (the per-view project + bin_sort that provide the bins are not); each view's time is
+    its median over the repetitions (a call's events also see any host stall before its launch)."""
     import torch
     from paper_2411_00771_amd import raster
     n = eng.n
@@ -82,7 +83,7 @@ def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=2
             e0.record()
             eng.contribution(c, gamma, c_sum=c_sum)
             e1.record()
-            times.append((rep, e0, e1))
+            times.append((rep, k, e0, e1))
             if rep == reps - 1:
                 flops += F_CON_EVAL * counts[k][0] + F_CON_CON * counts[k][1]
     c_avg = c_sum / len(cams)
@@ -91,12 +92,61 @@ def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=2
     bound, mask, removed = raster.trim_mask(c_avg, ratio)
     t1.record()
     torch.cuda.synchronize()
-    ms = [a.elapsed_time(b) for r, a, b in times if r == reps - 1]
+    ms = [float(np.median([a.elapsed_time(b) for r, kk, a, b in times if kk == k])) for k in range(len(cams))]
     per_view = float(np.mean(ms))
     return {"views": len(cams), "gamma": gamma, "ratio": ratio, "ms_per_view": round(per_view, 4),
             "views_per_s": round(1e3 / per_view, 2),
             "tflops": round(flops / (sum(ms) * 1e-3) / 1e12, 3),
-            "trim_ms": round(t0.elapsed_time(t1), 4), "removed": int(removed.item()), "bound": float(bound.item())}
+            "trim_ms": round(t0.elapsed_time(t1), 4), "removed": int(removed.item()),
+            "bound": float(bound.item())}, mask
+
+
+def camera_extent(cams):
+    """Scene extent as the 3DGS family sets it: 1.1 x the largest camera-centre distance from their mean."""
+    C = np.array([-np.asarray(c.R, np.float64).reshape(3, 3).T @ np.asarray(c.t, np.float64) for c in cams])
+    return 1.1 * float(np.linalg.norm(C - C.mean(0), axis=1).max())
+
+
+def bench_densify_action(params, cand_mask, trim_mask, dense_scale, reps=5):
+    """Densification action on the training step's candidate mask and the trimming mask: the plan, then
+    (after the output size is read back) the apply.  Each is event-timed; bytes are the algorithmic ones:
+    plan 23 B per surfel (mask, removal, log-scales, logit in; action and two slots out), apply
+    9 B per surfel (action, slots) + one read of every surviving surfel + one write of every output
+    surfel with its slot-map entry."""
+    import torch
+    from paper_2411_00771_amd import raster, scenes
+    n = params.n
+    _, _, z = scenes.densify_inputs(4242, n)
+    zt = torch.from_numpy(z).cuda()
+    K = (params.sh_degree + 1) ** 2
+    surfel_bytes = 4 * (3 + 2 + 4 + 1 + 3 * K)
+    t_plan, t_apply = [], []
+    plan = raster.densify_plan(params, cand_mask, trim_mask, dense_scale=dense_scale)
+    n_out = plan.n_out()
+    # outputs allocated once, outside the timed calls (the call itself allocates nothing)
+    out, src = raster.densify_apply(params, plan, zt, n_out=n_out)
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        plan = raster.densify_plan(params, cand_mask, trim_mask, dense_scale=dense_scale)
+        e[1].record()
+        n_out = plan.n_out()
+        e[2].record()
+        raster.densify_apply(params, plan, zt, n_out=n_out, out=out, src=src)
+        e[3].record()
+        torch.cuda.synchronize()
+        t_plan.append(e[0].elapsed_time(e[1]))
+        t_apply.append(e[2].elapsed_time(e[3]))
+    del out, src
+    cnt = plan.counts.cpu().numpy()
+    tp, ta = float(np.median(t_plan)), float(np.median(t_apply))
+    b_plan = 23.0 * n
+    b_apply = 9.0 * n + surfel_bytes * (n - cnt[3]) + (surfel_bytes + 4) * n_out
+    return {"surfels": n, "dense_scale": round(dense_scale, 4), "keep": int(cnt[0]), "clone": int(cnt[1]),
+            "split": int(cnt[2]), "removed": int(cnt[3]), "n_out": int(n_out),
+            "plan_ms": round(tp, 4), "apply_ms": round(ta, 4),
+            "plan_gbs": round(b_plan / (tp * 1e-3) / 1e9, 1), "apply_gbs": round(float(b_apply) / (ta * 1e-3) / 1e9, 1),
+            "apply_hbm_frac": round(float(b_apply) / (ta * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
 def bench_batched(steps, warmup, n=None):
@@ -222,6 +272,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contribution", action="store_true")
+    ap.add_argument("--no-densify-action", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -370,9 +421,13 @@ def main():
         "intersections_max": int(need),
         "roofline": roof,
     }
+    trim = None
     if not args.no_contribution:
-        out["contribution"] = bench_contribution(eng, params, cams, counts)
+        out["contribution"], trim = bench_contribution(eng, params, cams, counts)
         log(f"[bench] contribution/trim: {out['contribution']}")
+    if not args.no_densify_action:
+        out["densify_action"] = bench_densify_action(params, state.mask, trim, 0.01 * camera_extent(cams_all))
+        log(f"[bench] densify action: {out['densify_action']}")
     target0 = targets[0][0].cpu().numpy().astype(np.float64)
     del eng, grads, state, params, targets
     torch.cuda.empty_cache()

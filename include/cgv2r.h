@@ -281,6 +281,62 @@ size_t cgv2_trim_workspace(int64_t n);
 int cgv2_trim_mask(const float* c, int64_t n, float ratio, float* bound, uint8_t* mask, uint32_t* removed,
                    void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* Densification action.  Sec. 3.2 fixes which surfels are densified (the candidate bit 4 of
+ * cgv2_densify_state.mask: DGD high gradient and not elongated) and Sec. 3.3 which are removed (the
+ * cgv2_trim_mask mask); what a candidate becomes follows the 3DGS / 2DGS training the method builds on:
+ * a clone (an identical copy) when max(s_u, s_v) <= dense_scale, else a split into two children drawn
+ * from the surfel's own Gaussian, child c at mu + s_u z_c0 t_u + s_v z_c1 t_v with both scales divided
+ * by split_shrink and rotation, opacity and SH copied; a split surfel itself is removed. */
+typedef struct {
+  float dense_scale;   /* clone / split boundary on the larger scale (scene units) */
+  float min_opacity;   /* surfels with sigmoid(logit) < min_opacity are removed too (0 disables) */
+  float split_shrink;  /* scale divisor of split children (1.6 in 3DGS) */
+} cgv2_action_params;
+
+/* Output surfel set of cgv2_densify_apply: the layouts of cgv2_surfels with n = the capacity (stride of
+ * the planar arrays; sh[n][(deg+1)^2][3]).  Must not overlap the input set. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  float *mean, *log_scale, *quat, *opacity_logit, *sh;
+} cgv2_surfels_out;
+
+/* Workspace bytes for cgv2_densify_plan. */
+size_t cgv2_densify_plan_workspace(int64_t n);
+
+/* Plans the densification action of n surfels (n < 2^30).  Decisions are taken in FP64 on the float32
+ * parameters, in this order: remove when remove[i] != 0 (remove may be NULL) or sigmoid(logit) <
+ * min_opacity; else keep when bit 4 of mask[i] is clear; else clone when max(exp(log_scale)) <=
+ * dense_scale; else split.  Outputs (device):
+ *   actions[n]  0 keep, 1 clone, 2 split, 3 remove;
+ *   dst[2][n]   dst[0][i] = output slot of surfel i itself (keep, clone), dst[1][i] = first output slot
+ *               of its new surfel(s) (clone: 1, split: 2), 0xffffffff where none.  The output holds the
+ *               survivors in id order, then the new surfels in id order of their source;
+ *   counts[5]   (int64) keep, clone, split, removed, output size = keep + 2 clone + 2 split.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_densify_plan(const cgv2_surfels* s, const uint8_t* mask, const uint8_t* remove, const cgv2_action_params* prm,
+                      uint8_t* actions, uint32_t* dst, int64_t* counts, void* workspace, size_t ws_bytes,
+                      void* hip_stream);
+
+/* Applies a plan of cgv2_densify_plan (same s, actions, dst, counts): writes the new surfel set into out
+ * (out->n >= counts[4] is the caller's to ensure, e.g. by reading counts first; slots beyond out->n
+ * are dropped, never written out of bounds) and src[out->n] (device, u32): for each output slot,
+ * (source id << 2) | kind with kind 0 survivor, 1 clone copy, 2 split child 0, 3 split child 1 (the
+ * map cgv2_densify_gather re-lays other per-surfel arrays by).  z[n][2][2] (device, float32) holds the
+ * offsets of the two children of surfel i (standard-normal draws, read for split surfels only).
+ * Survivors and copies are bit-exact copies; a child's mean and log-scales are evaluated in FP64 and
+ * rounded once.  Only prm->split_shrink is read.  Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_densify_apply(const cgv2_surfels* s, const uint8_t* actions, const uint32_t* dst, const int64_t* counts,
+                       const float* z, const cgv2_action_params* prm, const cgv2_surfels_out* out, uint32_t* src,
+                       void* hip_stream);
+
+/* Re-lays a per-surfel float field of n surfels (channels C; blocked = 0: field[C][n] -> out[C][out_n],
+ * blocked = 1: field[n][C] -> out[out_n][C]) by the map src of cgv2_densify_apply.  zero_new = 1
+ * writes 0 into the new slots (copies and children: fresh optimiser moments), 0 copies the source.
+ * Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_densify_gather(const float* field, int64_t n, int32_t channels, int32_t blocked, const uint32_t* src,
+                        const int64_t* counts, int32_t zero_new, float* out, int64_t out_n, void* hip_stream);
+
 /* Error string for a CGV2_E* code; thread-local hipError_t of the last failing launch. */
 const char* cgv2_strerror(int code);
 int cgv2_last_hip_error(void);

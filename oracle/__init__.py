@@ -267,6 +267,31 @@ def densify_apply(P, actions, z, shrink=1.6):
     return res
 
 
+def densify_slots(actions):
+    """Output slots of a plan, by the order :func:`densify_apply` defines: dst[0][i] the slot of surfel i
+    itself (keep, clone), dst[1][i] the first slot of its new surfel(s), -1 where none; and per output
+    slot its source id and kind (0 survivor, 1 clone copy, 2 / 3 split child 0 / 1)."""
+    act = np.asarray(actions)
+    n = act.shape[0]
+    dst = np.full((2, n), -1, np.int64)
+    src, kind = [], []
+    for i in range(n):
+        if act[i] in (0, 1):
+            dst[0, i] = len(src)
+            src.append(i)
+            kind.append(0)
+    for i in range(n):
+        if act[i] == 1:
+            dst[1, i] = len(src)
+            src.append(i)
+            kind.append(1)
+        elif act[i] == 2:
+            dst[1, i] = len(src)
+            src += [i, i]
+            kind += [2, 3]
+    return dst, np.array(src, np.int64), np.array(kind, np.int64)
+
+
 def project_bwd(scene, cam, g):
     P = _params(scene)
     out = dict(mean=np.zeros_like(P["mean"]), log_scale=np.zeros_like(P["log_scale"]), quat=np.zeros_like(P["quat"]),

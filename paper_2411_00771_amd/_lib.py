@@ -20,7 +20,8 @@ EXPORTS = ["cgv2_project", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_ren
            "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
            "cgv2_project_bwd", "cgv2_densify_workspace",
            "cgv2_densify_stats", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
-           "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_strerror", "cgv2_last_hip_error"]
+           "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_densify_plan_workspace", "cgv2_densify_plan",
+           "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_strerror", "cgv2_last_hip_error"]
 
 P = ctypes.c_void_p
 
@@ -68,6 +69,15 @@ class DensifyState(ctypes.Structure):
                 ("counters", P), ("scale", P)]
 
 
+class ActionParams(ctypes.Structure):
+    _fields_ = [("dense_scale", ctypes.c_float), ("min_opacity", ctypes.c_float), ("split_shrink", ctypes.c_float)]
+
+
+class SurfelsOut(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mean", P), ("log_scale", P), ("quat", P),
+                ("opacity_logit", P), ("sh", P)]
+
+
 _lib = None
 
 
@@ -112,6 +122,12 @@ def lib():
                                              i64, ctypes.c_float, P, P, P, P, sz, P]),
         "cgv2_trim_workspace": (sz, [i64]),
         "cgv2_trim_mask": (ctypes.c_int, [P, i64, ctypes.c_float, P, P, P, P, sz, P]),
+        "cgv2_densify_plan_workspace": (sz, [i64]),
+        "cgv2_densify_plan": (ctypes.c_int, [ctypes.POINTER(Surfels), P, P, ctypes.POINTER(ActionParams), P, P, P, P,
+                                             sz, P]),
+        "cgv2_densify_apply": (ctypes.c_int, [ctypes.POINTER(Surfels), P, P, P, P, ctypes.POINTER(ActionParams),
+                                              ctypes.POINTER(SurfelsOut), P, P]),
+        "cgv2_densify_gather": (ctypes.c_int, [P, i64, i32, i32, P, P, i32, P, i64, P]),
         "cgv2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cgv2_last_hip_error": (ctypes.c_int, []),
     }

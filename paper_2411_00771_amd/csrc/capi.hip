@@ -31,6 +31,9 @@ bool surfels_ok(const cgv2_surfels* s) {
          (s->n == 0 || (s->mean && s->log_scale && s->quat && s->opacity_logit && s->sh));
 }
 
+// the densification action packs source ids into 30 bits
+bool action_surfels_ok(const cgv2_surfels* s) { return surfels_ok(s) && s->n < ((int64_t)1 << 30); }
+
 bool proj_ok(const cgv2_proj* p) {
   return p && p->rec && p->rect && p->radius && p->flags && p->visible && p->visible_start;
 }
@@ -276,6 +279,43 @@ int cgv2_trim_mask(const float* c, int64_t n, float ratio, float* bound, uint8_t
   if (!workspace || ws_bytes < cgv2_trim_workspace(n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
   const uint32_t k = (uint32_t)floor((double)ratio * (double)(n - 1));
   return hip_status(cgv2_launch_trim(c, n, k, bound, mask, removed, workspace, (hipStream_t)stream));
+}
+
+size_t cgv2_densify_plan_workspace(int64_t n) {
+  if (n < 0) return 0;
+  size_t off[kActionOffs];
+  return cgv2_action_ws_layout(n, off);
+}
+
+int cgv2_densify_plan(const cgv2_surfels* s, const uint8_t* mask, const uint8_t* remove, const cgv2_action_params* prm,
+                      uint8_t* actions, uint32_t* dst, int64_t* counts, void* workspace, size_t ws_bytes,
+                      void* stream) {
+  if (!action_surfels_ok(s) || !prm || !counts || (s->n > 0 && (!mask || !actions || !dst))) return CGV2_EINVAL;
+  if (!(prm->dense_scale >= 0.f) || !(prm->min_opacity >= 0.f && prm->min_opacity <= 1.f)) return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_densify_plan_workspace(s->n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_densify_plan(*s, mask, remove, *prm, actions, dst, counts, workspace,
+                                             (hipStream_t)stream));
+}
+
+int cgv2_densify_apply(const cgv2_surfels* s, const uint8_t* actions, const uint32_t* dst, const int64_t* counts,
+                       const float* z, const cgv2_action_params* prm, const cgv2_surfels_out* out, uint32_t* src,
+                       void* stream) {
+  if (!action_surfels_ok(s) || !prm || !counts || !out || !(prm->split_shrink > 0.f)) return CGV2_EINVAL;
+  if (out->n < 0 || out->n >= ((int64_t)1 << 31) || out->sh_degree != s->sh_degree) return CGV2_EINVAL;
+  if (s->n > 0 && (!actions || !dst || !z)) return CGV2_EINVAL;
+  if (out->n > 0 && (!out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->sh || !src))
+    return CGV2_EINVAL;
+  return hip_status(cgv2_launch_densify_apply(*s, actions, dst, counts, z, *prm, *out, src, (hipStream_t)stream));
+}
+
+int cgv2_densify_gather(const float* field, int64_t n, int32_t channels, int32_t blocked, const uint32_t* src,
+                        const int64_t* counts, int32_t zero_new, float* out, int64_t out_n, void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 30) || out_n < 0 || out_n >= ((int64_t)1 << 31) || channels < 1 || !counts ||
+      (blocked != 0 && blocked != 1))
+    return CGV2_EINVAL;
+  if (n > 0 && out_n > 0 && (!field || !src || !out)) return CGV2_EINVAL;
+  return hip_status(cgv2_launch_densify_gather(field, n, channels, blocked, src, counts, zero_new ? 1 : 0, out, out_n,
+                                               (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -12,7 +12,7 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
 // Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
-constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3;
+constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2;
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
@@ -46,3 +46,14 @@ hipError_t cgv2_launch_contribution_final(const cgv2_proj& p, const cgv2::CamPac
 size_t cgv2_trim_ws_layout(int64_t n, size_t* off);
 hipError_t cgv2_launch_trim(const float* c, int64_t n, uint32_t k, float* bound, uint8_t* mask, uint32_t* removed,
                             void* ws, hipStream_t st);
+
+// densification action (action.hip)
+size_t cgv2_action_ws_layout(int64_t n, size_t* off);
+hipError_t cgv2_launch_densify_plan(const cgv2_surfels& s, const uint8_t* mask, const uint8_t* remove,
+                                    const cgv2_action_params& prm, uint8_t* actions, uint32_t* dst, int64_t* counts,
+                                    void* ws, hipStream_t st);
+hipError_t cgv2_launch_densify_apply(const cgv2_surfels& s, const uint8_t* actions, const uint32_t* dst,
+                                     const int64_t* counts, const float* z, const cgv2_action_params& prm,
+                                     const cgv2_surfels_out& out, uint32_t* src, hipStream_t st);
+hipError_t cgv2_launch_densify_gather(const float* f, int64_t n, int C, int blocked, const uint32_t* src,
+                                      const int64_t* counts, int zero_new, float* out, int64_t cap, hipStream_t st);

@@ -73,23 +73,55 @@ __global__ __launch_bounds__(kSelBlock) void k_sel_hist(const float* __restrict_
   part[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSelBlock) void k_sel_pick(const uint32_t* __restrict__ part, int nblocks, int shift,
-                                                       uint32_t* __restrict__ state) {
-  __shared__ uint32_t tot[256];
+// One workgroup of kPickThreads: the per-workgroup histograms are summed by kPickThreads / 256 groups
+// of threads with kPickUnroll independent loads in flight each (the sum is latency-bound); a scan over
+// the 256 bins then finds the digit whose count range holds the rank sought.
+constexpr int kPickThreads = 1024;
+constexpr int kPickUnroll = 8;
+
+__global__ __launch_bounds__(kPickThreads) void k_sel_pick(const uint32_t* __restrict__ part, int nblocks, int shift,
+                                                          uint32_t* __restrict__ state) {
+  constexpr int kGroups = kPickThreads / 256;
+  __shared__ uint32_t tot[kGroups][256];
+  __shared__ uint32_t wsum[4];
+  const uint32_t k = state[2];  // read by every thread before any write below
+  const int bin = threadIdx.x & 255, grp = threadIdx.x >> 8;
+  uint32_t acc[kPickUnroll] = {};
+  int b = grp;
+  for (; b + (kPickUnroll - 1) * kGroups < nblocks; b += kPickUnroll * kGroups) {
+#pragma unroll
+    for (int u = 0; u < kPickUnroll; ++u) acc[u] += part[(int64_t)(b + u * kGroups) * 256 + bin];
+  }
+  for (; b < nblocks; b += kGroups) acc[0] += part[(int64_t)b * 256 + bin];
   uint32_t t = 0;
-  for (int b = 0; b < nblocks; ++b) t += part[(int64_t)b * 256 + threadIdx.x];
-  tot[threadIdx.x] = t;
+#pragma unroll
+  for (int u = 0; u < kPickUnroll; ++u) t += acc[u];
+  tot[grp][bin] = t;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t k = state[2], below = 0;
-    int d = 0;
-    for (; d < 255; ++d) {
-      if (below + tot[d] > k) break;
-      below += tot[d];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t c = 0, x = 0;
+  if (threadIdx.x < 256) {
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) c += tot[g][threadIdx.x];
+    x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
     }
-    state[0] |= (uint32_t)d << shift;
-    state[1] |= 255u << shift;
-    state[2] = k - below;
+    if (lane == 63) wsum[w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t off = 0;
+    for (int q = 0; q < w; ++q) off += wsum[q];
+    const uint32_t incl = off + x, below = incl - c;
+    // digit d: below(d) <= k < below(d) + count(d); the last digit also takes a rank past the total
+    if (below <= k && (k < incl || threadIdx.x == 255)) {
+      state[0] |= (uint32_t)threadIdx.x << shift;
+      state[1] |= 255u << shift;
+      state[2] = k - below;
+    }
   }
 }
 
@@ -175,7 +207,7 @@ hipError_t cgv2_launch_trim(const float* c, int64_t n, uint32_t k, float* bound,
   hipLaunchKernelGGL(cgv2::k_sel_init, dim3(1), dim3(64), 0, st, state, k);
   for (int shift = 24; shift >= 0; shift -= 8) {
     hipLaunchKernelGGL(cgv2::k_sel_hist, dim3((unsigned)nb), dim3(cgv2::kSelBlock), 0, st, c, n, state, shift, part);
-    hipLaunchKernelGGL(cgv2::k_sel_pick, dim3(1), dim3(cgv2::kSelBlock), 0, st, part, nb, shift, state);
+    hipLaunchKernelGGL(cgv2::k_sel_pick, dim3(1), dim3(cgv2::kPickThreads), 0, st, part, nb, shift, state);
   }
   hipLaunchKernelGGL(cgv2::k_trim_apply, dim3((unsigned)nb), dim3(cgv2::kSelBlock), 0, st, c, n, state, mask, cnt);
   hipLaunchKernelGGL(cgv2::k_trim_count, dim3(1), dim3(cgv2::kSelBlock), 0, st, cnt, nb, state, bound, removed);

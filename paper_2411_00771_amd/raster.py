@@ -303,6 +303,91 @@ def trim_mask(c, ratio: float):
     return bound, mask, removed
 
 
+class DensifyPlan:
+    """Device outputs of cgv2_densify_plan: actions [n] (0 keep, 1 clone, 2 split, 3 remove), dst [2][n]
+    (int32-stored u32 slots), counts [5] int64 (keep, clone, split, removed, output size)."""
+
+    def __init__(self, actions, dst, counts):
+        self.actions, self.dst, self.counts = actions, dst, counts
+
+    def n_out(self) -> int:
+        """Output size (reads the device count: a synchronisation)."""
+        return int(self.counts[4].item())
+
+
+def _action_params(dense_scale, min_opacity, split_shrink):
+    prm = _lib.ActionParams()
+    prm.dense_scale, prm.min_opacity, prm.split_shrink = float(dense_scale), float(min_opacity), float(split_shrink)
+    return prm
+
+
+def densify_plan(params: Params, mask, remove=None, dense_scale: float = 0.01, min_opacity: float = 0.005,
+                 ws=None) -> DensifyPlan:
+    """Per-surfel densification action (Sec. 3.2 candidates = bit 4 of ``mask``, Sec. 3.3 removal =
+    ``remove``), stream-ordered; nothing is read back."""
+    L = _lib.lib()
+    n = params.n
+    dev = params.mean.device
+    actions = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    dst = torch.empty((2, max(n, 1)), dtype=torch.int32, device=dev)
+    counts = torch.empty(5, dtype=torch.int64, device=dev)
+    need = max(L.cgv2_densify_plan_workspace(n), 256)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    s = params.struct()
+    check(L.cgv2_densify_plan(ctypes.byref(s), ptr(mask), ptr(remove),
+                              ctypes.byref(_action_params(dense_scale, min_opacity, 1.6)), ptr(actions), ptr(dst),
+                              ptr(counts), ptr(ws), ws.numel(), _stream()), "cgv2_densify_plan")
+    return DensifyPlan(actions[:n], dst[:, :n] if n else dst[:, :0], counts)
+
+
+def densify_apply(params: Params, plan: DensifyPlan, z, split_shrink: float = 1.6, n_out: Optional[int] = None,
+                  out: Optional[Params] = None, src=None):
+    """The new surfel set of a plan: (Params, src) with src [n_out] the slot -> (source << 2 | kind) map.
+    z [n][2][2] float32 (device) are the children's standard-normal offsets.  n_out defaults to the
+    plan's count (read from the device); out / src may be given (n_out surfels, n_out int32)."""
+    L = _lib.lib()
+    n = params.n
+    if n_out is None:
+        n_out = plan.n_out() if out is None else out.n
+    dev = params.mean.device
+    K = (params.sh_degree + 1) ** 2
+    if out is None:
+        out = Params(torch.empty((3, n_out), device=dev), torch.empty((2, n_out), device=dev),
+                     torch.empty((4, n_out), device=dev), torch.empty(n_out, device=dev),
+                     torch.empty((n_out, K, 3), device=dev), params.sh_degree)
+    assert out.n == n_out and out.sh_degree == params.sh_degree
+    if src is None:
+        src = torch.empty(max(n_out, 1), dtype=torch.int32, device=dev)
+    assert src.dtype == torch.int32 and src.numel() >= n_out
+    if n:
+        assert z.is_cuda and z.dtype == torch.float32 and z.is_contiguous() and z.numel() == 4 * n
+    o = _lib.SurfelsOut()
+    o.n, o.sh_degree = n_out, params.sh_degree
+    o.mean, o.log_scale, o.quat = ptr(out.mean), ptr(out.log_scale), ptr(out.quat)
+    o.opacity_logit, o.sh = ptr(out.opacity_logit), ptr(out.sh)
+    s = params.struct()
+    check(L.cgv2_densify_apply(ctypes.byref(s), ptr(plan.actions), ptr(plan.dst), ptr(plan.counts),
+                               ptr(z) if n else None, ctypes.byref(_action_params(0.0, 0.0, split_shrink)),
+                               ctypes.byref(o), ptr(src), _stream()), "cgv2_densify_apply")
+    return out, src[:n_out]
+
+
+def densify_gather(field, src, plan: DensifyPlan, n_out: int, blocked: bool = False, zero_new: bool = False):
+    """Re-lays a per-surfel float32 field (planar [C][n] / [n], or blocked [n][C]) into the new set."""
+    L = _lib.lib()
+    assert field.is_cuda and field.dtype == torch.float32 and field.is_contiguous()
+    if blocked:
+        n, C = field.shape[0], int(field[0].numel()) if field.shape[0] else int(np.prod(field.shape[1:]))
+        out = torch.empty((n_out,) + tuple(field.shape[1:]), dtype=torch.float32, device=field.device)
+    else:
+        n, C = field.shape[-1], int(np.prod(field.shape[:-1])) if field.dim() > 1 else 1
+        out = torch.empty(tuple(field.shape[:-1]) + (n_out,), dtype=torch.float32, device=field.device)
+    check(L.cgv2_densify_gather(ptr(field), n, C, 1 if blocked else 0, ptr(src), ptr(plan.counts),
+                                1 if zero_new else 0, ptr(out), n_out, _stream()), "cgv2_densify_gather")
+    return out
+
+
 # ------------------------------------------------------------------------------------------------
 # autograd form
 # ------------------------------------------------------------------------------------------------

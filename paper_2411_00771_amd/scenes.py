@@ -358,6 +358,17 @@ def perturbed(scene: Scene, seed: int, pos_sigma: float = 0.05, sh_sigma: float 
     return s
 
 
+def densify_inputs(seed: int, n: int, cand_frac: float = 0.05, remove_frac: float = 0.025):
+    """Random inputs of a densification action over n surfels: a candidate mask (bit 4, the densify state's
+    candidate bit), a removal mask (uint8 0/1) and the split children's standard-normal offsets
+    z[n][2][2] (float32)."""
+    rng = np.random.default_rng(seed)
+    mask = np.where(rng.random(n) < cand_frac, 4, 0).astype(np.uint8) | rng.integers(0, 4, n).astype(np.uint8)
+    remove = (rng.random(n) < remove_frac).astype(np.uint8)
+    z = rng.standard_normal((n, 2, 2)).astype(np.float32)
+    return mask, remove, z
+
+
 def poisson_requests(seed: int, rate: float, duration: float, resolutions):
     """Arrival times (s) and a resolution index per request, open loop."""
     rng = np.random.default_rng(seed)

@@ -46,6 +46,9 @@ def test_strerror_and_workspace_sizes():
     assert L.cgv2_render_bwd_workspace(-1, 2) == 0 and L.cgv2_render_bwd_workspace(10, 0) == 0
     assert L.cgv2_loss_workspace(0, 10, 1) == 0
     assert L.cgv2_densify_workspace(10, 1) > 0
+    # plan workspace: 24 bytes per workgroup of 2048 surfels, 256-byte aligned parts
+    assert L.cgv2_densify_plan_workspace(0) > 0 and L.cgv2_densify_plan_workspace(-1) == 0
+    assert L.cgv2_densify_plan_workspace(10 ** 7) >= 24 * (10 ** 7 // 2048)
 
 
 def _fake_proj():
@@ -104,6 +107,26 @@ def test_argument_validation_returns_einval():
     assert L.cgv2_trim_mask(ws, 10, 1.5, None, ws, None, ws, 1 << 30, None) == EINVAL
     assert L.cgv2_trim_mask(ws, 0, 0.1, None, ws, None, ws, 1 << 30, None) == EINVAL
     assert L.cgv2_trim_mask(ws, 10, 0.1, None, None, None, ws, 1 << 30, None) == EINVAL
+    # densification action: n beyond 2^30, missing outputs, bad thresholds, mismatched output degree
+    ap = _lib.ActionParams(0.01, 0.005, 1.6)
+    big = _lib.Surfels(1 << 30, 3, *[ctypes.c_void_p(256)] * 5)
+    assert L.cgv2_densify_plan(ctypes.byref(big), ws, None, ctypes.byref(ap), ws, ws, ws, ws, 1 << 40,
+                               None) == EINVAL
+    assert L.cgv2_densify_plan(ctypes.byref(s), ws, None, ctypes.byref(ap), None, ws, ws, ws, 1 << 30,
+                               None) == EINVAL
+    assert L.cgv2_densify_plan(ctypes.byref(s), ws, None, ctypes.byref(_lib.ActionParams(0.01, 1.5, 1.6)), ws, ws,
+                               ws, ws, 1 << 30, None) == EINVAL
+    so = _lib.SurfelsOut(20, 3, *[ctypes.c_void_p(256)] * 5)
+    assert L.cgv2_densify_apply(ctypes.byref(s), ws, ws, ws, ws, ctypes.byref(_lib.ActionParams(0.01, 0.0, 0.0)),
+                                ctypes.byref(so), ws, None) == EINVAL
+    so2 = _lib.SurfelsOut(20, 2, *[ctypes.c_void_p(256)] * 5)
+    assert L.cgv2_densify_apply(ctypes.byref(s), ws, ws, ws, ws, ctypes.byref(ap), ctypes.byref(so2), ws,
+                                None) == EINVAL
+    assert L.cgv2_densify_apply(ctypes.byref(s), ws, ws, ws, ws, ctypes.byref(ap), ctypes.byref(so), None,
+                                None) == EINVAL
+    assert L.cgv2_densify_gather(ws, 10, 0, 0, ws, ws, 0, ws, 20, None) == EINVAL
+    assert L.cgv2_densify_gather(ws, 10, 3, 2, ws, ws, 0, ws, 20, None) == EINVAL
+    assert L.cgv2_densify_gather(None, 10, 3, 0, ws, ws, 0, ws, 20, None) == EINVAL
     prm = _lib.DensifyParams(0.9, 0.05, 2e-4)
     st = _lib.DensifyState()
     assert L.cgv2_densify_stats(ctypes.byref(s), ctypes.byref(p), ctypes.byref(g), 1, ctypes.byref(prm),
@@ -135,6 +158,9 @@ def test_small_workspace_returns_eworkspace():
                             None) == _lib.CGV2_EWORKSPACE
     assert L.cgv2_loss(v, v, 1, 64, 64, 0.2, v, v, v, v, L.cgv2_loss_workspace(64, 64, 1) - 1,
                        None) == _lib.CGV2_EWORKSPACE
+    ap = _lib.ActionParams(0.01, 0.005, 1.6)
+    assert L.cgv2_densify_plan(ctypes.byref(s), v, None, ctypes.byref(ap), v, v, v, v,
+                               L.cgv2_densify_plan_workspace(10) - 1, None) == _lib.CGV2_EWORKSPACE
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

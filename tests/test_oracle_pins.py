@@ -494,3 +494,27 @@ def test_p15_densify_actions_and_apply_by_hand():
     assert np.array_equal(out["log_scale"][:, :3], log_scale[:, [0, 1, 1]])
     keep, clone, split = (act == 0).sum(), (act == 1).sum(), (act == 2).sum()
     assert out["mean"].shape[1] == keep + 2 * clone + 2 * split
+
+
+def test_p15_slots_follow_the_apply_order():
+    rng = np.random.default_rng(15)
+    n = 40
+    act = rng.integers(0, 4, n).astype(np.int32)
+    dst, src, kind = oracle.densify_slots(act)
+    # the apply with ids planted in the opacity field and z = 0 reproduces the slot order
+    P = dict(mean=np.zeros((3, n)), log_scale=np.zeros((2, n)), quat=np.tile([[1.0], [0], [0], [0]], (1, n)),
+             opacity_logit=np.arange(n, dtype=np.float64), sh=np.zeros((1, 3, n)), sh_degree=0)
+    out = oracle.densify_apply(P, act, np.zeros((n, 2, 2)))
+    assert np.array_equal(out["opacity_logit"], src.astype(np.float64))
+    assert len(src) == (act == 0).sum() + 2 * (act == 1).sum() + 2 * (act == 2).sum()
+    for i in range(n):
+        assert (dst[0, i] >= 0) == (act[i] in (0, 1)) and (dst[1, i] >= 0) == (act[i] in (1, 2))
+        if dst[0, i] >= 0:
+            assert src[dst[0, i]] == i and kind[dst[0, i]] == 0
+        if act[i] == 1:
+            assert src[dst[1, i]] == i and kind[dst[1, i]] == 1
+        if act[i] == 2:
+            assert list(src[dst[1, i]:dst[1, i] + 2]) == [i, i] and list(kind[dst[1, i]:dst[1, i] + 2]) == [2, 3]
+    # survivors first, new surfels after, each group in id order
+    surv = (act == 0) | (act == 1)
+    assert np.all(np.diff(src[:surv.sum()]) > 0) and np.all(np.diff(src[surv.sum():]) >= 0)
