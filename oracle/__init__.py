@@ -9,6 +9,7 @@ its reverse mode, SSIM, the Eq. 3 contribution) and in :func:`densify_stats`,
 :func:`average_contribution` and :func:`trim_threshold` below (Eq. 2, the
 elongation rate of Sec. 3.2, Eq. 4 and the trimming bound of Sec. 3.3) and in
 :func:`densify_actions` / :func:`densify_apply` (the densification action).
+``oracle.visibility`` holds the visibility-frequency crop-volume estimate of Sec. 4.
 
 Parity-unpinned readings (the paper fixes none of them; they are pinned to the
 mathematics instead): pixel-centre sampling, the screen low-pass filter width,

@@ -18,6 +18,10 @@ P13 contribution (Eq. 3): closed forms for one facing surfel and for two stacked
 P14 Eq. 4 average and the trimming bound on hand-worked arrays
 P15 densification action on a hand-worked six-surfel set: keep, clone, split (identity and quarter-turn
     rotations), trimmed and low-opacity removal, output order and counts
+P16 visibility frequency (Sec. 4 crop volume): the sphere-image box in closed form on the axis and
+    against dense silhouette sampling off the axis; hand-placed visible / hidden points (behind the
+    camera, between two pixel samples, off the image edge); counts as sums over views; the crop
+    threshold, height range and ground coordinates under two transforms
 """
 import math
 
@@ -518,3 +522,92 @@ def test_p15_slots_follow_the_apply_order():
     # survivors first, new surfels after, each group in id order
     surv = (act == 0) | (act == 1)
     assert np.all(np.diff(src[:surv.sum()]) > 0) and np.all(np.diff(src[surv.sum():]) >= 0)
+
+
+# ---- P16: visibility frequency for the crop volume --------------------------------------------------
+
+def _cam100(R=None, t=None, W=100, H=100, f=100.0):
+    return scenes.Camera(W, H, f, f, W / 2.0, H / 2.0, np.eye(3) if R is None else np.asarray(R, np.float64),
+                         np.zeros(3) if t is None else np.asarray(t, np.float64))
+
+
+def test_p16_sphere_box_closed_form_on_axis():
+    from oracle import visibility as vis
+    for Z, rho in ((10.0, 1.0), (3.0, 2.5), (100.0, 0.01)):
+        u0, u1, v0, v1 = vis.sphere_image_bbox(np.array(0.0), np.array(0.0), np.array(Z), rho, 100.0, 80.0, 50.0, 40.0)
+        half = rho / math.sqrt(Z * Z - rho * rho)   # tan of the half-angle asin(rho / Z)
+        assert np.isclose(u0, 50.0 - 100.0 * half, rtol=0, atol=1e-12)
+        assert np.isclose(u1, 50.0 + 100.0 * half, rtol=0, atol=1e-12)
+        assert np.isclose(v0, 40.0 - 80.0 * half, rtol=0, atol=1e-12)
+        assert np.isclose(v1, 40.0 + 80.0 * half, rtol=0, atol=1e-12)
+
+
+def test_p16_sphere_box_against_silhouette_sampling():
+    from oracle import visibility as vis
+    rng = np.random.default_rng(16)
+    # dense sphere surface samples: the projected samples fill the image, whose box is the exact box
+    k = 400
+    th, ph = np.meshgrid(np.linspace(0, np.pi, k), np.linspace(0, 2 * np.pi, 2 * k), indexing="ij")
+    S = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 0).reshape(3, -1)
+    for _ in range(20):
+        X, Y = rng.uniform(-20, 20, 2)
+        Z = rng.uniform(2, 40)
+        rho = rng.uniform(0.05, 0.9) * min(Z, 2.0)
+        pts = np.array([[X], [Y], [Z]]) + rho * S
+        u = 120.0 * pts[0] / pts[2] + 64.0
+        v = 90.0 * pts[1] / pts[2] + 48.0
+        u0, u1, v0, v1 = vis.sphere_image_bbox(X, Y, Z, rho, 120.0, 90.0, 64.0, 48.0)
+        scale = max(1.0, abs(u0), abs(u1), abs(v0), abs(v1))
+        assert u.min() >= u0 - 1e-9 * scale and u.max() <= u1 + 1e-9 * scale
+        assert v.min() >= v0 - 1e-9 * scale and v.max() <= v1 + 1e-9 * scale
+        # the box is touched: sampling resolution ~ (pi / k)^2 / 2 of the extent
+        tol = 2e-4 * (u1 - u0) + 1e-9
+        assert u.min() - u0 < tol and u1 - u.max() < tol
+        assert v.min() - v0 < 2e-4 * (v1 - v0) + 1e-9 and v1 - v.max() < 2e-4 * (v1 - v0) + 1e-9
+
+
+def test_p16_visible_mask_by_hand():
+    from oracle import visibility as vis
+    cam = _cam100()
+    # image centre (u = 50 lies between the samples 49.5 and 50.5: a 0.7 px reach covers both, 0.3 px
+    # none); behind the camera; closer than znear
+    P = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [10.0, -10.0, 0.1]])
+    v, f = vis.visible(P, cam, 0.01, 0.7)
+    assert list(v) == [True, False, False] and not f.any()
+    assert list(vis.visible(P, cam, 0.01, 0.3)[0]) == [False, False, False]
+    # a tiny footprint between the samples x = 59.5 and 60.5 (centre u = 60.0, reach 0.3 px): hidden;
+    # moved to u = 60.3 it covers 60.5: visible.  (Z = 10, f = 100: X = (u - 50) / 10; v = 50.5 sits
+    # on a sample row.)
+    P = np.array([[1.0, 1.03], [0.05, 0.05], [10.0, 10.0]])
+    v, f = vis.visible(P, cam, 1e-4, 0.3)
+    assert list(v) == [False, True] and not f.any()
+    # centre 3 px left of the image (u = -3): a reach of 3.6 px covers the sample 0.5 of column 0, 3.2 px
+    # does not (rho = 0 leaves only the filter disc)
+    P = np.array([[-5.3], [0.0], [10.0]])
+    assert list(vis.visible(P, cam, 0.0, 3.6)[0]) == [True]
+    assert list(vis.visible(P, cam, 0.0, 3.2)[0]) == [False]
+    # a sphere reaching the camera plane is visible whatever its image
+    P = np.array([[30.0], [0.0], [0.5]])
+    assert list(vis.visible(P, cam, 1.0, 0.3)[0]) == [True]
+
+
+def test_p16_counts_are_sums_over_views_and_crop():
+    from oracle import visibility as vis
+    rng = np.random.default_rng(160)
+    P = rng.uniform(-5, 5, (3, 500))
+    P[2] += 20.0
+    cams = [_cam100(t=[rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-5, 5)]) for _ in range(7)]
+    cnt, frag = vis.visibility_count(P, cams, 0.05, 0.7)
+    assert np.array_equal(cnt, sum(vis.visible(P, c, 0.05, 0.7)[0].astype(np.int64) for c in cams))
+    assert cnt.min() >= 0 and cnt.max() <= 7 and frag.sum() == 0
+    tau = 4
+    keep, G, h0, h1 = vis.crop_volume(P, cnt, tau, np.hstack([np.eye(3), np.zeros((3, 1))]))
+    P32 = P.astype(np.float32).astype(np.float64)
+    assert np.array_equal(keep, cnt >= tau)
+    assert np.array_equal(G, P32[:2, keep]) and h0 == P32[2, keep].min() and h1 == P32[2, keep].max()
+    # a transform that makes y the height axis and shifts it
+    T = np.array([[1.0, 0, 0, 0], [0, 0, 1.0, 0], [0, 1.0, 0, -2.0]])
+    keep, G, h0, h1 = vis.crop_volume(P, cnt, tau, T)
+    assert np.array_equal(G, np.stack([P32[0, keep], P32[2, keep]])) and h0 == P32[1, keep].min() - 2.0
+    keep, G, h0, h1 = vis.crop_volume(P, cnt, 8, T)
+    assert not keep.any() and G.shape == (2, 0) and math.isnan(h0)
