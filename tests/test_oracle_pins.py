@@ -22,6 +22,9 @@ P16 visibility frequency (Sec. 4 crop volume): the sphere-image box in closed fo
     against dense silhouette sampling off the axis; hand-placed visible / hidden points (behind the
     camera, between two pixel samples, off the image edge); counts as sums over views; the crop
     threshold, height range and ground coordinates under two transforms
+P17 serving storage: float16 rounding at known values, the importance partition, the nearest codeword
+    against explicit loops and by construction (ties to the smaller index), the Lloyd update by hand
+    (an empty codeword kept), the non-increasing k-means error, and decode(pack) within float16 rounding
 """
 import math
 
@@ -611,3 +614,69 @@ def test_p16_counts_are_sums_over_views_and_crop():
     assert np.array_equal(G, np.stack([P32[0, keep], P32[2, keep]])) and h0 == P32[1, keep].min() - 2.0
     keep, G, h0, h1 = vis.crop_volume(P, cnt, 8, T)
     assert not keep.any() and G.shape == (2, 0) and math.isnan(h0)
+
+
+# ---- P17: serving storage (float16 + vector quantization) ------------------------------------------
+
+def test_p17_float16_and_partition():
+    from oracle import compact as oc
+    # IEEE half: 1/3 -> 0x3555, the largest finite 65504, 2049 rounds to the even 2048, 2051 to 2052
+    v = np.array([1 / 3, 65504.0, 2049.0, 2051.0, -0.0], np.float32).astype(np.float16)
+    assert list(v.view(np.uint16)) == [0x3555, 0x7BFF, 0x6800, 0x6802, 0x8000]
+    order, nf = oc.order_partition(np.array([1, 0, 0, 1, 0, 1], np.uint8))
+    assert list(order) == [1, 2, 4, 0, 3, 5] and nf == 3
+
+
+def test_p17_nearest_codeword():
+    from oracle import compact as oc
+    rng = np.random.default_rng(17)
+    C = np.array([[0.0, 0.0], [10.0, 0.0], [0.0, 10.0], [10.0, 10.0]])
+    X = C[[3, 0, 2, 1, 1]] + rng.uniform(-1, 1, (5, 2))
+    codes, best, gap = oc.vq_assign(X, C)
+    assert list(codes) == [3, 0, 2, 1, 1] and np.all(gap > 0.1)
+    # equal distances: the smaller index
+    codes, _, gap = oc.vq_assign(np.array([[5.0, 0.0]]), C)
+    assert codes[0] == 0 and gap[0] == 0.0
+    # against explicit loops
+    X = rng.normal(size=(50, 6))
+    C = rng.normal(size=(9, 6))
+    codes, best, _ = oc.vq_assign(X, C)
+    for i in range(50):
+        d = [sum((X[i, k] - C[j, k]) ** 2 for k in range(6)) for j in range(9)]
+        assert codes[i] == int(np.argmin(d)) and math.isclose(best[i], min(d), rel_tol=1e-12)
+
+
+def test_p17_lloyd_update_and_monotone_error():
+    from oracle import compact as oc
+    X = np.array([[0.0, 0.0], [2.0, 0.0], [10.0, 10.0], [12.0, 10.0], [11.0, 13.0]])
+    C0 = np.array([[1.0, 1.0], [10.0, 10.0], [50.0, 50.0]])
+    codes, _, _ = oc.vq_assign(X, C0)
+    assert list(codes) == [0, 0, 1, 1, 1]
+    C1, cnt = oc.vq_update(X, codes, C0)
+    assert np.allclose(C1, [[1.0, 0.0], [11.0, 11.0], [50.0, 50.0]]) and list(cnt) == [2, 3, 0]
+    rng = np.random.default_rng(170)
+    Y = np.concatenate([rng.normal(c, 0.3, (200, 3)) for c in rng.uniform(-5, 5, (12, 3))])
+    _, _, errs = oc.kmeans(Y, 12, 8)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:]))
+
+
+def test_p17_decode_of_pack_within_half_rounding():
+    from oracle import compact as oc
+    sc = scenes.tiny_scene(17, 600, sh_degree=2)
+    P = dict(mean=sc.mean, log_scale=sc.log_scale, quat=sc.quat, opacity_logit=sc.opacity_logit, sh=sc.sh,
+             sh_degree=2)
+    q = (np.arange(600) % 3 == 0).astype(np.uint8)
+    order, nf = oc.order_partition(q)
+    X = sc.sh[:, :, order[nf:]].transpose(2, 0, 1).reshape(600 - nf, 27)
+    C, codes, _ = oc.kmeans(X, 16, 3)
+    c = oc.pack(P, order, nf, codes, C)
+    d = oc.decode(c)
+    assert np.array_equal(d["mean"], sc.mean[:, order])
+    for k in ("log_scale", "quat"):
+        ref = np.asarray(P[k], np.float64)[:, order]
+        assert np.all(np.abs(d[k] - ref) <= 2.0 ** -11 * np.abs(ref) + 2.0 ** -24)
+    ref = sc.sh[:, :, order[:nf]].astype(np.float64)
+    assert np.all(np.abs(d["sh"][:, :, :nf] - ref) <= 2.0 ** -11 * np.abs(ref) + 2.0 ** -24)
+    # a quantized surfel decodes to its float16 codeword
+    cw = C[codes[0]].astype(np.float32).astype(np.float16).astype(np.float32).reshape(9, 3)
+    assert np.array_equal(d["sh"][:, :, nf], cw)
