@@ -149,6 +149,56 @@ def bench_densify_action(params, cand_mask, trim_mask, dense_scale, reps=5):
             "apply_hbm_frac": round(float(b_apply) / (ta * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
+def bench_crop(reps=3, rho=0.8, filter_px=2.1213, tau=3):
+    """Visibility-frequency crop volume (Sec. 4) on its quoted scale: 31.4 M points, 958 views at
+    1920x1080 over 1.47 km^2.  Times the visibility count (median of reps; points in Morton order, as
+    stored; one pass in a random order for comparison) and the crop statistics."""
+    import torch
+    from paper_2411_00771_amd import _lib, crop, scenes
+    t0 = time.time()
+    w = scenes.crop_workload()
+    P, cams = w["points"], w["cameras"]
+    gen_s = time.time() - t0
+    m, V = P.shape[1], len(cams)
+    pt = torch.from_numpy(P).cuda()
+    arr = _lib.camera_array(cams)
+    cnt = torch.zeros(m, dtype=torch.int32, device="cuda")
+    crop.visibility_count(pt, arr, rho, filter_px, count=cnt)  # warm-up
+    ms = []
+    for _ in range(reps):
+        cnt.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        crop.visibility_count(pt, arr, rho, filter_px, count=cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    perm = torch.randperm(m, device="cuda")
+    pr = pt[:, perm].contiguous()
+    cr = torch.zeros(m, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    crop.visibility_count(pr, arr, rho, filter_px, count=cr)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_rand = e0.elapsed_time(e1)
+    same = bool(torch.equal(cr, cnt[perm]))
+    del pr, cr, perm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    keep, ground, (h0, h1) = crop.crop_volume(pt, cnt, tau, np.hstack([np.eye(3), np.zeros((3, 1))]))
+    e1.record()
+    torch.cuda.synchronize()
+    t = float(np.median(ms))
+    c = cnt.float()
+    return {"points": m, "views": V, "resolution": [cams[0].width, cams[0].height], "radius": rho,
+            "filter_px": filter_px, "generate_s": round(gen_s, 1), "count_ms": round(t, 3),
+            "decisions_per_s": round(m * V / (t * 1e-3), 1), "count_ms_random_order": round(ms_rand, 3),
+            "random_order_same_counts": same, "crop_ms_incl_readback": round(e0.elapsed_time(e1), 3),
+            "mean_views_per_point": round(float(c.mean()), 2), "kept": int(ground.shape[1]), "tau": tau,
+            "height_range": [round(h0, 3), round(h1, 3)]}
+
+
 def bench_batched(steps, warmup, n=None):
     """Differentiation form: 8 views per launch through the autograd Functions at 4 M surfels, against the
     plain single-view path over the same 8 views on the same scene."""
@@ -273,6 +323,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contribution", action="store_true")
     ap.add_argument("--no-densify-action", action="store_true")
+    ap.add_argument("--no-crop", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -429,6 +480,11 @@ def main():
         out["densify_action"] = bench_densify_action(params, state.mask, trim, 0.01 * camera_extent(cams_all))
         log(f"[bench] densify action: {out['densify_action']}")
     target0 = targets[0][0].cpu().numpy().astype(np.float64)
+    if not args.no_crop:
+        log("[bench] crop-volume visibility pass (31.4M points, 958 views)")
+        out["crop"] = bench_crop()
+        log(f"[bench] crop: {out['crop']}")
+        torch.cuda.empty_cache()
     del eng, grads, state, params, targets
     torch.cuda.empty_cache()
     if not args.no_batched:

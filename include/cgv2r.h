@@ -76,6 +76,23 @@ typedef struct {
   const float *mean, *log_scale, *quat, *opacity_logit, *sh;
 } cgv2_surfels;
 
+/* Serving storage of a trained set (Sec. 3.3: SH degree 2 from the start; the appendix's vector-tree
+ * quantization: the least important surfels' SH replaced by a codebook row, everything else but the
+ * positions in float16).  uint16_t arrays hold IEEE float16 bits (codes and codebook rows excepted).
+ *   mean[3][n] float32; log_scale[2][n], quat[4][n], opacity_logit[n] float16;
+ *   sh[n_full][(deg+1)^2][3] float16 for the surfels [0, n_full);
+ *   code[n - n_full]: codebook row of surfel n_full + j (a row >= codebook_size culls the surfel, as a
+ *   non-finite parameter would);
+ *   codebook[codebook_size][(deg+1)^2][3] float16.
+ * The decoded float32 values go through the projection unchanged: a compact set projects exactly like
+ * its decoded float32 copy. */
+typedef struct {
+  int64_t n, n_full;
+  int32_t sh_degree, codebook_size;
+  const float* mean;
+  const uint16_t *log_scale, *quat, *opacity_logit, *sh, *code, *codebook;
+} cgv2_surfels_compact;
+
 /* Per-view projection.  rec[V][n][24] is written for visible surfels only:
  *   0,1  cx_hi, cy_hi   integer part of the projected centre (pixels)
  *   2,3  cx_lo, cy_lo   remainder: centre = hi + lo
@@ -176,6 +193,11 @@ typedef struct {
  * low-pass filter disc of radius k sqrt(2)/2 px (Sec. 3.2).
  * Errors: CGV2_EINVAL (nulls, bad sizes), CGV2_EHIP. */
 int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* hip_stream);
+
+/* cgv2_project for a compact set (serving).  Same outputs and rules.  Errors: CGV2_EINVAL (also
+ * n_full outside [0, n], codebook_size outside [1, 65536] with n_full < n), CGV2_EHIP. */
+int cgv2_project_compact(const cgv2_surfels_compact* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj,
+                         void* hip_stream);
 
 /* Workspace bytes for cgv2_bin_sort with the given capacity, view count, tiles per view and surfel
  * count (0 for invalid arguments). */
@@ -336,6 +358,36 @@ int cgv2_densify_apply(const cgv2_surfels* s, const uint8_t* actions, const uint
  * Errors: CGV2_EINVAL, CGV2_EHIP. */
 int cgv2_densify_gather(const float* field, int64_t n, int32_t channels, int32_t blocked, const uint32_t* src,
                         const int64_t* counts, int32_t zero_new, float* out, int64_t out_n, void* hip_stream);
+
+/* Workspace bytes for cgv2_visibility_count (the views' FP64 camera table). */
+size_t cgv2_visibility_workspace(int32_t V);
+
+/* Visible frequency of m ground-truth points (Sec. 4, crop-volume estimate of the evaluation protocol):
+ * count[i] += the number of the V views in which point i's visible mask is set (the caller zeroes count
+ * first).  Each point is a small isotropic Gaussian: its footprint is the image of the sphere of radius
+ * 'radius' (scene units) around it, hulled with a disc of filter_px pixels around its projected centre;
+ * it is visible when its centre depth exceeds znear and a pixel sample (i + 0.5, j + 0.5) of the view
+ * lies in the footprint's bounding box (no occlusion test; a sphere reaching the camera plane, depth <=
+ * radius, is visible).  All decisions in FP64.  points[3][m] (device, float32); cams: V host structs,
+ * each with its own width and height and znear > 0 (bg unused).  Any point order gives the same
+ * counts; spatially coherent order (e.g. scan or tile order) is much faster, since whole workgroups of
+ * neighbouring points then skip a view or count it at once.
+ * Errors: CGV2_EINVAL (m < 0, V < 1, radius < 0, filter_px < 0, a camera without positive size, focal
+ * lengths or znear), CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_visibility_count(const float* points, int64_t m, const cgv2_camera* cams, int32_t V, float radius,
+                          float filter_px, uint32_t* count, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes for cgv2_crop_volume. */
+size_t cgv2_crop_workspace(int64_t m);
+
+/* Crop statistics of Sec. 4 from the visible frequencies: keep[i] = count[i] >= tau; for the kept
+ * points, (x, y, h) = T p with T (host, 3x4 row-major, FP64) the ground transform: ground[2][m] (device,
+ * FP64, stride m) receives (x, y) of the kept points in id order in its first *kept columns (for the
+ * alpha shape), hrange[2] (device, FP64) = min and max h over them (NaN when none is kept), *kept
+ * (device, int64) their number.  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_crop_volume(const float* points, int64_t m, const uint32_t* count, uint32_t tau, const double* T,
+                     uint8_t* keep, double* ground, double* hrange, int64_t* kept, void* workspace, size_t ws_bytes,
+                     void* hip_stream);
 
 /* Error string for a CGV2_E* code; thread-local hipError_t of the last failing launch. */
 const char* cgv2_strerror(int code);

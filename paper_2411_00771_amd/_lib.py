@@ -16,12 +16,13 @@ TILE = 16
 REC_FLOATS = 24
 F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ["cgv2_project", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
+EXPORTS = ["cgv2_project", "cgv2_project_compact", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
            "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
            "cgv2_project_bwd", "cgv2_densify_workspace",
            "cgv2_densify_stats", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
            "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_densify_plan_workspace", "cgv2_densify_plan",
-           "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_strerror", "cgv2_last_hip_error"]
+           "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_visibility_workspace", "cgv2_visibility_count",
+           "cgv2_crop_workspace", "cgv2_crop_volume", "cgv2_strerror", "cgv2_last_hip_error"]
 
 P = ctypes.c_void_p
 
@@ -35,6 +36,12 @@ class Camera(ctypes.Structure):
 class Surfels(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mean", P), ("log_scale", P), ("quat", P),
                 ("opacity_logit", P), ("sh", P)]
+
+
+class SurfelsCompact(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_full", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("codebook_size", ctypes.c_int32), ("mean", P), ("log_scale", P), ("quat", P),
+                ("opacity_logit", P), ("sh", P), ("code", P), ("codebook", P)]
 
 
 class Proj(ctypes.Structure):
@@ -96,6 +103,8 @@ def lib():
     i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "cgv2_project": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Camera), i32, ctypes.POINTER(Proj), P]),
+        "cgv2_project_compact": (ctypes.c_int, [ctypes.POINTER(SurfelsCompact), ctypes.POINTER(Camera), i32,
+                                                ctypes.POINTER(Proj), P]),
         "cgv2_bin_sort_workspace": (sz, [i64, i32, i32, i64]),
         "cgv2_bin_sort": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Camera), i32, i64, ctypes.POINTER(Bins),
                                          P, sz, P]),
@@ -128,6 +137,12 @@ def lib():
         "cgv2_densify_apply": (ctypes.c_int, [ctypes.POINTER(Surfels), P, P, P, P, ctypes.POINTER(ActionParams),
                                               ctypes.POINTER(SurfelsOut), P, P]),
         "cgv2_densify_gather": (ctypes.c_int, [P, i64, i32, i32, P, P, i32, P, i64, P]),
+        "cgv2_visibility_workspace": (sz, [i32]),
+        "cgv2_visibility_count": (ctypes.c_int, [P, i64, ctypes.POINTER(Camera), i32, ctypes.c_float, ctypes.c_float, P,
+                                                 P, sz, P]),
+        "cgv2_crop_workspace": (sz, [i64]),
+        "cgv2_crop_volume": (ctypes.c_int, [P, i64, P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), P, P, P, P, P,
+                                            sz, P]),
         "cgv2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cgv2_last_hip_error": (ctypes.c_int, []),
     }

@@ -28,29 +28,6 @@ constexpr uint32_t kNone = 0xffffffffu;
 enum : uint32_t { A_KEEP = 0, A_CLONE = 1, A_SPLIT = 2, A_REMOVE = 3 };
 enum : uint32_t { S_SURVIVOR = 0, S_COPY = 1, S_CHILD0 = 2, S_CHILD1 = 3 };
 
-// Exclusive scan over the workgroup (kABlock threads); 'total' receives the workgroup sum.
-template <typename T>
-__device__ __forceinline__ T block_exscan(T v, T* lds, T& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) lds[w] = x;
-  __syncthreads();
-  T off = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kABlock / 64; ++k) {
-    if (k < w) off += lds[k];
-    tot += lds[k];
-  }
-  __syncthreads();
-  total = tot;
-  return off + x - v;
-}
-
 // The action of surfel i, decided in FP64 on the float32 parameters.
 __device__ __forceinline__ uint32_t action_of(const uint8_t* __restrict__ mask, const uint8_t* __restrict__ remove,
                                               const float* __restrict__ ls, const float* __restrict__ logit,
@@ -84,7 +61,7 @@ __global__ __launch_bounds__(kABlock) void k_act_count(const uint8_t* __restrict
     }
   }
   unsigned long long tot;
-  block_exscan(c, lds, tot);
+  block_exscan<kABlock>(c, lds, tot);
   if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = (uint32_t)((tot >> (16 * threadIdx.x)) & 0xffffu);
 }
 
@@ -108,7 +85,7 @@ __global__ __launch_bounds__(kABlock) void k_act_scan(const uint32_t* __restrict
     const unsigned long long v = (unsigned long long)(q[A_KEEP] + q[A_CLONE]) |
                                  ((unsigned long long)(q[A_CLONE] + 2u * q[A_SPLIT]) << 32);
     unsigned long long tot;
-    const unsigned long long ex = block_exscan(v, lds, tot) + carry;
+    const unsigned long long ex = block_exscan<kABlock>(v, lds, tot) + carry;
     if (b < nb) offs[b] = make_uint2((uint32_t)ex, (uint32_t)(ex >> 32));
     carry += tot;
   }
@@ -155,7 +132,7 @@ __global__ __launch_bounds__(kABlock) void k_act_dst(const uint8_t* __restrict__
   for (int k = 0; k < kAItems; ++k)
     v += (a[k] <= A_CLONE ? 1u : 0u) + (a[k] == A_CLONE ? 1u << 16 : a[k] == A_SPLIT ? 2u << 16 : 0u);
   uint32_t tot;
-  const uint32_t ex = block_exscan(v, lds, tot);
+  const uint32_t ex = block_exscan<kABlock>(v, lds, tot);
   const uint2 o = offs[blockIdx.x];
   const uint32_t survivors = (uint32_t)(counts[A_KEEP] + counts[A_CLONE]);
   uint32_t rs = o.x + (ex & 0xffffu);

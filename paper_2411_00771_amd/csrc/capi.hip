@@ -124,6 +124,23 @@ const char* cgv2_strerror(int code) {
 
 int cgv2_last_hip_error(void) { return g_last_hip; }
 
+int cgv2_project_compact(const cgv2_surfels_compact* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj,
+                         void* stream) {
+  if (!s || s->n < 0 || s->n >= (int64_t)0xffffffff || s->sh_degree < 0 || s->sh_degree > 3 || !cams_ok(cams, V) ||
+      !proj_ok(proj) || s->n_full < 0 || s->n_full > s->n)
+    return CGV2_EINVAL;
+  if (s->n > 0 && (!s->mean || !s->log_scale || !s->quat || !s->opacity_logit)) return CGV2_EINVAL;
+  if (s->n_full > 0 && !s->sh) return CGV2_EINVAL;
+  if (s->n_full < s->n && (!s->code || !s->codebook || s->codebook_size < 1 || s->codebook_size > 65536))
+    return CGV2_EINVAL;
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_project_compact(*s, pack(cams, v0, cnt), *proj, (hipStream_t)stream));
+    if (rc) return rc;
+  }
+  return CGV2_OK;
+}
+
 int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* stream) {
   if (!surfels_ok(s) || !cams_ok(cams, V) || !proj_ok(proj)) return CGV2_EINVAL;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
@@ -316,6 +333,43 @@ int cgv2_densify_gather(const float* field, int64_t n, int32_t channels, int32_t
   if (n > 0 && out_n > 0 && (!field || !src || !out)) return CGV2_EINVAL;
   return hip_status(cgv2_launch_densify_gather(field, n, channels, blocked, src, counts, zero_new ? 1 : 0, out, out_n,
                                                (hipStream_t)stream));
+}
+
+size_t cgv2_visibility_workspace(int32_t V) { return V < 1 ? 0 : cgv2_vis_ws_layout(V); }
+
+int cgv2_visibility_count(const float* points, int64_t m, const cgv2_camera* cams, int32_t V, float radius,
+                          float filter_px, uint32_t* count, void* workspace, size_t ws_bytes, void* stream) {
+  if (m < 0 || V < 1 || !cams || !(radius >= 0.f) || !(filter_px >= 0.f) || (m > 0 && (!points || !count)))
+    return CGV2_EINVAL;
+  for (int v = 0; v < V; ++v)
+    if (cams[v].width <= 0 || cams[v].height <= 0 || !(cams[v].fx > 0.f) || !(cams[v].fy > 0.f) ||
+        !(cams[v].znear > 0.f))
+      return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_visibility_workspace(V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  const hipStream_t st = (hipStream_t)stream;
+  for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
+    const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
+    const int rc = hip_status(cgv2_launch_vis_table(pack(cams, v0, cnt), V, radius, filter_px, workspace, st));
+    if (rc) return rc;
+  }
+  return hip_status(cgv2_launch_vis_count(points, m, V, radius, filter_px, count, workspace, st));
+}
+
+size_t cgv2_crop_workspace(int64_t m) {
+  if (m < 0) return 0;
+  size_t off[kCropOffs];
+  return cgv2_crop_ws_layout(m, off);
+}
+
+int cgv2_crop_volume(const float* points, int64_t m, const uint32_t* count, uint32_t tau, const double* T,
+                     uint8_t* keep, double* ground, double* hrange, int64_t* kept, void* workspace, size_t ws_bytes,
+                     void* stream) {
+  if (m < 0 || m >= ((int64_t)1 << 32) || !T || !hrange || !kept ||
+      (m > 0 && (!points || !count || !keep || !ground)))
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_crop_workspace(m)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_crop(points, m, count, tau, T, keep, ground, hrange, kept, workspace,
+                                     (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -117,6 +117,30 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
     p[i] = v;
 }
 
+// Exclusive scan over a workgroup of kThreads threads (a multiple of 64); lds holds kThreads / 64
+// values; 'total' receives the workgroup sum.  Every thread of the workgroup must call it.
+template <int kThreads, typename T>
+__device__ __forceinline__ T block_exscan(T v, T* lds, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kThreads / 64; ++k) {
+    if (k < w) off += lds[k];
+    tot += lds[k];
+  }
+  __syncthreads();
+  total = tot;
+  return off + x - v;
+}
+
 // Block -> tile mapping.  Hardware dispatches workgroup b to XCD b % 8.  Here XCD x receives the
 // runs of kXcdChunk consecutive tiles with run index = x (mod 8): neighbouring tiles of a run share
 // that XCD's L2, while the runs of every XCD are spread over the whole image.  (Giving each XCD one

@@ -8,11 +8,13 @@
 #include "cgv2r_device.h"
 
 hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st);
+hipError_t cgv2_launch_project_compact(const cgv2_surfels_compact& s, const cgv2::CamPack& cams, const cgv2_proj& p,
+                                      hipStream_t st);
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
 // Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
-constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2;
+constexpr int kBinsortOffs = 9, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2, kCropOffs = 2;
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
@@ -57,3 +59,13 @@ hipError_t cgv2_launch_densify_apply(const cgv2_surfels& s, const uint8_t* actio
                                      const cgv2_surfels_out& out, uint32_t* src, hipStream_t st);
 hipError_t cgv2_launch_densify_gather(const float* f, int64_t n, int C, int blocked, const uint32_t* src,
                                       const int64_t* counts, int zero_new, float* out, int64_t cap, hipStream_t st);
+
+// visibility-frequency crop volume (crop.hip)
+constexpr int kVisMaxViews = 4096;  // views per k_vis_count launch (its LDS list of edge views)
+size_t cgv2_vis_ws_layout(int V);
+hipError_t cgv2_launch_vis_table(const cgv2::CamPack& cams, int V, double rho, double rf, void* ws, hipStream_t st);
+hipError_t cgv2_launch_vis_count(const float* pts, int64_t m, int V, double rho, double rf, uint32_t* count,
+                                 void* ws, hipStream_t st);
+size_t cgv2_crop_ws_layout(int64_t m, size_t* off);
+hipError_t cgv2_launch_crop(const float* pts, int64_t m, const uint32_t* count, uint32_t tau, const double* T,
+                            uint8_t* keep, double* ground, double* hrange, int64_t* kept, void* ws, hipStream_t st);

@@ -160,17 +160,51 @@ __device__ __forceinline__ void rot_from_quat(const double q[4], double R[9]) {
   R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
 }
 
-__device__ __forceinline__ void load_geom(const cgv2_surfels& s, const DevCam& c, int64_t i, Geom& g) {
-  const int64_t n = s.n;
-  g.su = (double)expf(s.log_scale[i]);
-  g.sv = (double)expf(s.log_scale[n + i]);
-  g.o = 1.0 / (1.0 + (double)expf(-s.opacity_logit[i]));
-  const double q[4] = {s.quat[i], s.quat[n + i], s.quat[2 * n + i], s.quat[3 * n + i]};
+// Parameter sources of the forward projection.  Both hand the same float32 values to the same
+// arithmetic, so a compact set projects bit for bit like its decoded float32 copy.
+struct FullSource {
+  const cgv2_surfels& s;
+  __device__ int64_t n() const { return s.n; }
+  __device__ float mean(int k, int64_t i) const { return s.mean[k * s.n + i]; }
+  __device__ float log_scale(int k, int64_t i) const { return s.log_scale[k * s.n + i]; }
+  __device__ float quat(int k, int64_t i) const { return s.quat[k * s.n + i]; }
+  __device__ float opacity_logit(int64_t i) const { return s.opacity_logit[i]; }
+  __device__ bool valid(int64_t) const { return true; }
+  template <int N>
+  __device__ void sh(int64_t i, float (&f)[N]) const { load_row<N>(s.sh + i * N, f); }
+};
+
+__device__ __forceinline__ float half_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+
+// Serving storage (Sec. 3.3 and the appendix's vector-tree quantization): float16 shape, rotation and
+// opacity; float16 SH for the surfels [0, n_full), a codebook row for the rest.
+struct CompactSource {
+  const cgv2_surfels_compact& s;
+  __device__ int64_t n() const { return s.n; }
+  __device__ float mean(int k, int64_t i) const { return s.mean[k * s.n + i]; }
+  __device__ float log_scale(int k, int64_t i) const { return half_bits(s.log_scale[k * s.n + i]); }
+  __device__ float quat(int k, int64_t i) const { return half_bits(s.quat[k * s.n + i]); }
+  __device__ float opacity_logit(int64_t i) const { return half_bits(s.opacity_logit[i]); }
+  __device__ bool valid(int64_t i) const { return i < s.n_full || s.code[i - s.n_full] < (uint32_t)s.codebook_size; }
+  template <int N>
+  __device__ void sh(int64_t i, float (&f)[N]) const {
+    const uint16_t* p = i < s.n_full ? s.sh + i * N : s.codebook + (int64_t)s.code[i - s.n_full] * N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) f[j] = half_bits(p[j]);
+  }
+};
+
+template <class Src>
+__device__ __forceinline__ void load_geom(const Src& s, const DevCam& c, int64_t i, Geom& g) {
+  g.su = (double)expf(s.log_scale(0, i));
+  g.sv = (double)expf(s.log_scale(1, i));
+  g.o = 1.0 / (1.0 + (double)expf(-s.opacity_logit(i)));
+  const double q[4] = {s.quat(0, i), s.quat(1, i), s.quat(2, i), s.quat(3, i)};
   g.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   const double iq = 1.0 / g.qlen;
   for (int k = 0; k < 4; ++k) g.qn[k] = q[k] * iq;
   rot_from_quat(g.qn, g.Rw);
-  const double mu[3] = {s.mean[i], s.mean[n + i], s.mean[2 * n + i]};
+  const double mu[3] = {s.mean(0, i), s.mean(1, i), s.mean(2, i)};
   double cu[3], cv[3], ncd[3];
   for (int r = 0; r < 3; ++r) {
     const double R0 = c.R[3 * r], R1 = c.R[3 * r + 1], R2 = c.R[3 * r + 2];
@@ -225,16 +259,16 @@ __device__ __forceinline__ void homography(const double* M, Homog& h) {
 }
 
 // Projects surfel i into view v; returns whether it is binned (visible).
-template <int DEG>
-__device__ __forceinline__ bool project_one(const cgv2_surfels& s, const DevCam& c, int v, int64_t i,
+template <int DEG, class Src>
+__device__ __forceinline__ bool project_one(const Src& s, const DevCam& c, int v, int64_t i,
                                             const cgv2_proj& out) {
-  const int64_t n = s.n;
+  const int64_t n = s.n();
   const int64_t vi = (int64_t)v * n + i;
   uint16_t* rect = out.rect + 4 * vi;
   Geom g;
   load_geom(s, c, i, g);
   unsigned fl = 0;
-  bool finite = isfinite(g.o) && isfinite(g.su) && isfinite(g.sv) && isfinite(g.qlen) && g.qlen > 0;
+  bool finite = isfinite(g.o) && isfinite(g.su) && isfinite(g.sv) && isfinite(g.qlen) && g.qlen > 0 && s.valid(i);
   for (int k = 0; k < 9; ++k) finite = finite && isfinite(g.M[k]);
   const double k2 = 2.0 * log(255.0 * g.o);
   if (!finite) fl = CGV2_F_NONFINITE;
@@ -295,7 +329,7 @@ __device__ __forceinline__ bool project_one(const cgv2_surfels& s, const DevCam&
   float Y[K];
   sh_basis<DEG>(g.dir[0], g.dir[1], g.dir[2], Y, nullptr);
   float f[3 * K];
-  load_row<3 * K>(s.sh + (int64_t)i * 3 * K, f);
+  s.template sh<3 * K>(i, f);
   float col[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
@@ -323,7 +357,14 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project(cgv2_surfels s, CamPack cams, cgv2_proj out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = cams.v0 + (int)blockIdx.y;
-  if (i < s.n) project_one<DEG>(s, cams.c[blockIdx.y], v, i, out);
+  if (i < s.n) project_one<DEG>(FullSource{s}, cams.c[blockIdx.y], v, i, out);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_compact(cgv2_surfels_compact s, CamPack cams, cgv2_proj out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = cams.v0 + (int)blockIdx.y;
+  if (i < s.n) project_one<DEG>(CompactSource{s}, cams.c[blockIdx.y], v, i, out);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -375,7 +416,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
     gls[1] = gr.d_log_scale[n + i];
     glo = gr.d_opacity_logit[i];
     Geom g;
-    load_geom(s, c, i, g);
+    load_geom(FullSource{s}, c, i, g);
 
     // ---- record -> (alpha, beta, gamma) -> M; the common scale of the coefficients leaves every
     // output unchanged, so it is held constant
@@ -485,6 +526,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cam
 }
 
 }  // namespace cgv2
+
+hipError_t cgv2_launch_project_compact(const cgv2_surfels_compact& s, const cgv2::CamPack& cams, const cgv2_proj& p,
+                                      hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)cams.count);
+  switch (s.sh_degree) {
+    case 0: hipLaunchKernelGGL(cgv2::k_project_compact<0>, grid, dim3(256), 0, st, s, cams, p); break;
+    case 1: hipLaunchKernelGGL(cgv2::k_project_compact<1>, grid, dim3(256), 0, st, s, cams, p); break;
+    case 2: hipLaunchKernelGGL(cgv2::k_project_compact<2>, grid, dim3(256), 0, st, s, cams, p); break;
+    default: hipLaunchKernelGGL(cgv2::k_project_compact<3>, grid, dim3(256), 0, st, s, cams, p); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p, hipStream_t st) {
   if (s.n == 0) return hipSuccess;

@@ -408,14 +408,35 @@ def poisson_requests(seed: int, rate: float, duration: float, resolutions):
 SERVE_RESOLUTIONS = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
 
 
+def morton_order(points: np.ndarray, bits: int = 21) -> np.ndarray:
+    """Permutation that puts points [3][n] in 3-D Morton (octree) order, with cubic cells: the order in
+    which octree-indexed point clouds are stored."""
+    P = points.astype(np.float64)
+    lo = P.min(1, keepdims=True)
+    span = max(float((P.max(1, keepdims=True) - lo).max()), 1e-30)
+    q = ((P - lo) / span * ((1 << bits) - 1)).astype(np.uint64)
+
+    def spread(v):  # bit k of v -> bit 3k
+        v = v & np.uint64(0x1FFFFF)
+        v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+        v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+        return (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+
+    code = spread(q[0]) | (spread(q[1]) << np.uint64(1)) | (spread(q[2]) << np.uint64(2))
+    return np.argsort(code, kind="stable")
+
+
 def crop_workload(n_points: int = 31_400_000, views: int = 958, width: int = 1920, height: int = 1080,
                   seed: int = 5):
     """Visibility-frequency crop-volume estimate of the evaluation protocol (Sec. 4): the scene it is
     quoted on covers 1.47 km^2 with 958 training views and 31.4 M ground-truth points, rendered at
     1080p.  Stand-in: a 1.47 km^2 synthetic city (L = 1212 m), a point cloud on its surfaces and
-    aerial cameras over it."""
+    aerial cameras over it.  The points are stored in 3-D Morton (octree) order."""
     city = make_city(seed, L=1212.0)
     pts = city_points(seed + 500, n_points, city)
+    pts = np.ascontiguousarray(pts[:, morton_order(pts)])
     cams = aerial_cameras(seed + 1000, city, count=views, width=width, height=height)
     return dict(name=f"crop-{n_points // 1000}k-{views}v-{width}x{height}", points=pts, cameras=cams, city=city)
 

@@ -49,6 +49,9 @@ def test_strerror_and_workspace_sizes():
     # plan workspace: 24 bytes per workgroup of 2048 surfels, 256-byte aligned parts
     assert L.cgv2_densify_plan_workspace(0) > 0 and L.cgv2_densify_plan_workspace(-1) == 0
     assert L.cgv2_densify_plan_workspace(10 ** 7) >= 24 * (10 ** 7 // 2048)
+    # visibility: one FP64 camera table row per view; crop: 20 bytes per workgroup of 2048 points
+    assert L.cgv2_visibility_workspace(958) >= 958 * 56 * 8 and L.cgv2_visibility_workspace(0) == 0
+    assert L.cgv2_crop_workspace(10 ** 7) >= 20 * (10 ** 7 // 2048) and L.cgv2_crop_workspace(-1) == 0
 
 
 def _fake_proj():
@@ -127,6 +130,19 @@ def test_argument_validation_returns_einval():
     assert L.cgv2_densify_gather(ws, 10, 0, 0, ws, ws, 0, ws, 20, None) == EINVAL
     assert L.cgv2_densify_gather(ws, 10, 3, 2, ws, ws, 0, ws, 20, None) == EINVAL
     assert L.cgv2_densify_gather(None, 10, 3, 0, ws, ws, 0, ws, 20, None) == EINVAL
+    # visibility: V < 1, negative radius, a camera without znear; crop: missing transform or outputs
+    vc = _lib.Camera()
+    vc.width, vc.height, vc.fx, vc.fy, vc.znear = 64, 48, 50.0, 50.0, 0.2
+    assert L.cgv2_visibility_count(ws, 10, ctypes.byref(vc), 0, 0.1, 1.0, ws, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_visibility_count(ws, 10, ctypes.byref(vc), 1, -0.1, 1.0, ws, ws, 1 << 30, None) == EINVAL
+    bad_near = _lib.Camera()
+    bad_near.width, bad_near.height, bad_near.fx, bad_near.fy = 64, 48, 50.0, 50.0
+    assert L.cgv2_visibility_count(ws, 10, ctypes.byref(bad_near), 1, 0.1, 1.0, ws, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_visibility_count(ws, 10, ctypes.byref(vc), 1, 0.1, 1.0, None, ws, 1 << 30, None) == EINVAL
+    T = (ctypes.c_double * 12)()
+    assert L.cgv2_crop_volume(ws, 10, ws, 1, None, ws, ws, ws, ws, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_crop_volume(ws, 10, ws, 1, T, None, ws, ws, ws, ws, 1 << 30, None) == EINVAL
+    assert L.cgv2_crop_volume(ws, -1, ws, 1, T, ws, ws, ws, ws, ws, 1 << 30, None) == EINVAL
     prm = _lib.DensifyParams(0.9, 0.05, 2e-4)
     st = _lib.DensifyState()
     assert L.cgv2_densify_stats(ctypes.byref(s), ctypes.byref(p), ctypes.byref(g), 1, ctypes.byref(prm),
@@ -161,6 +177,13 @@ def test_small_workspace_returns_eworkspace():
     ap = _lib.ActionParams(0.01, 0.005, 1.6)
     assert L.cgv2_densify_plan(ctypes.byref(s), v, None, ctypes.byref(ap), v, v, v, v,
                                L.cgv2_densify_plan_workspace(10) - 1, None) == _lib.CGV2_EWORKSPACE
+    vc = _lib.Camera()
+    vc.width, vc.height, vc.fx, vc.fy, vc.znear = 64, 48, 50.0, 50.0, 0.2
+    assert L.cgv2_visibility_count(v, 10, ctypes.byref(vc), 1, 0.1, 1.0, v, v, L.cgv2_visibility_workspace(1) - 1,
+                                   None) == _lib.CGV2_EWORKSPACE
+    T = (ctypes.c_double * 12)()
+    assert L.cgv2_crop_volume(v, 5000, v, 1, T, v, v, v, v, v, L.cgv2_crop_workspace(5000) - 1,
+                              None) == _lib.CGV2_EWORKSPACE
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
