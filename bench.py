@@ -310,6 +310,78 @@ def bench_serving(seconds, warmup_s, slots, n=None):
     return out
 
 
+def bench_storage(seconds=10.0, warmup_s=2.0, slots=4, n=None, ratio=0.4, codebook_size=8192, iters=10):
+    """Serving storage (Sec. 3.3 SH degree 2; the appendix's vector-tree quantization): the serving scene
+    with SH of degree 2, its Eq. 3/4 contributions over 16 orbit views, the compression (partition,
+    k-means on the matrix cores, float16 packing), then the Poisson trace against the compact set and
+    against its float32 source."""
+    import torch
+    from paper_2411_00771_amd import raster, scenes, server, storage
+    w = scenes.workload(3, n_override=n)
+    city = w["city"]
+    sc = scenes.city_scene(3, w["scene"].n, L=1600.0, sh_degree=2, city=city)
+    params = raster.Params.from_scene(sc, torch.device("cuda:0"))
+    rng = np.random.default_rng(3005)
+    views = [scenes.orbit_camera(rng, city, 1280, 720) for _ in range(16)]
+    eng = raster.Engine(sc.n, 1280, 720, 1)
+    need = max(eng.fit_capacity(params, eng.cams([c])) for c in views)
+    eng.set_capacity(int(need * 1.25) + 4096)
+    c_sum = torch.zeros(sc.n, device="cuda:0")
+    for c in views:
+        cc = eng.cams([c])
+        eng.project(params, cc)
+        eng.bin_sort(cc)
+        eng.contribution(cc, 0.5, c_sum=c_sum)
+    c_avg = c_sum / len(views)
+    del eng
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cp, info = storage.compress(params, c_avg, ratio=ratio, codebook_size=codebook_size, iters=iters)
+    torch.cuda.synchronize()
+    t_comp = time.perf_counter() - t0
+    # one assignment pass, event-timed: m x K x D multiply-adds on the matrix cores
+    D = 27
+    rows = cp.order[cp.n_full:]
+    x = params.sh.reshape(sc.n, D)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    storage.vq_assign(x, D, rows, info["codebook"])
+    e1.record()
+    torch.cuda.synchronize()
+    t_assign = e0.elapsed_time(e1)
+    m, K = rows.numel(), info["codebook_size"]
+    flops = 2.0 * m * K * 28  # padded to 7 MFMA steps of 4
+    full_bytes = sum(t.numel() * 4 for t in (params.mean, params.log_scale, params.quat, params.opacity_logit,
+                                             params.sh))
+    out = {"surfels": sc.n, "sh_degree": 2, "quantized": m, "codebook_size": K, "iters": iters,
+           "compress_s": round(t_comp, 3), "assign_ms": round(t_assign, 3),
+           "assign_tflops": round(flops / (t_assign * 1e-3) / 1e12, 2),
+           "bytes_full": full_bytes, "bytes_compact": cp.nbytes(), "ratio": round(cp.nbytes() / full_bytes, 3)}
+    reqs = [r for r in w["requests"] if r[0] < seconds]
+    rng = np.random.default_rng(3004)
+    cams = [scenes.orbit_camera(rng, city, *scenes.SERVE_RESOLUTIONS[k]) for _, k in reqs]
+    arrivals = [t for t, _ in reqs]
+    for name, ps in (("compact", cp), ("float32", params)):
+        srv = server.Server(ps, max_slots=slots, arena_bytes=32 << 30, intersections_per_pixel=3.0,
+                            keep_results=False)
+        for c in cams[:8]:
+            srv.render_alone(c)
+        srv.finished.clear()
+        done, wall = server.run_trace(srv, cams, arrivals)
+        t_first = min(r.arrival for r in done)
+        win = [r for r in done if r.arrival - t_first >= warmup_s and r.error is None]
+        lat = np.array([r.latency for r in win])
+        px = sum(r.cam.width * r.cam.height for r in win)
+        span = max(r.done_t for r in win) - min(r.arrival for r in win)
+        out[name] = {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "mpix_per_s": round(px / span / 1e6, 2)}
+        log(f"[bench] storage serving {name}: {out[name]}")
+        del srv
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +396,7 @@ def main():
     ap.add_argument("--no-contribution", action="store_true")
     ap.add_argument("--no-densify-action", action="store_true")
     ap.add_argument("--no-crop", action="store_true")
+    ap.add_argument("--no-storage", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -495,6 +568,11 @@ def main():
     if not args.no_serve:
         log("[bench] serving form (5M surfels, Poisson 200/s, mixed resolutions)")
         out["serving"] = bench_serving(args.serve_seconds, 2.0, args.serve_slots)
+        torch.cuda.empty_cache()
+    if not args.no_storage:
+        log("[bench] serving storage (SH degree 2, float16 + vector quantization)")
+        out["storage"] = bench_storage()
+        log(f"[bench] storage: {out['storage']}")
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on one view (CPU)")

@@ -389,6 +389,62 @@ int cgv2_crop_volume(const float* points, int64_t m, const uint32_t* count, uint
                      uint8_t* keep, double* ground, double* hrange, int64_t* kept, void* workspace, size_t ws_bytes,
                      void* hip_stream);
 
+/* ---- building the serving storage (see cgv2_surfels_compact) ---------------------------------------
+ * x[*][D] below is any float32 array of D-vectors (e.g. cgv2_surfels.sh, D = 3 (deg+1)^2) and rows[m]
+ * (device, u32) selects the vectors taken part, each < the number of vectors in x.  D must be one of
+ * 1-4, 9-12, 25-28, 45-48 (the SH sizes of degrees 0-3, padded to whole 4-wide MFMA steps). */
+
+/* Workspace bytes for cgv2_compact_order. */
+size_t cgv2_compact_order_workspace(int64_t n);
+
+/* Stable partition of n surfels by quantize[n] (0 = keep its SH, else = replace it by a codeword):
+ * order[n] (device, u32) = source id of each storage slot, kept surfels first, both groups in id order;
+ * *n_full (device, int64) = number kept.  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_compact_order(const uint8_t* quantize, int64_t n, uint32_t* order, int64_t* n_full, void* workspace,
+                       size_t ws_bytes, void* hip_stream);
+
+/* Codebook start for K codewords: codebook[j] = x[rows[floor(j m / K)]] (m >= 1).
+ * Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_vq_init(const float* x, int32_t D, const uint32_t* rows, int64_t m, int32_t K, float* codebook,
+                 void* hip_stream);
+
+/* Workspace bytes for cgv2_vq_assign. */
+size_t cgv2_vq_assign_workspace(int32_t K);
+
+/* Nearest codeword (squared Euclidean distance) of each selected vector: code[m] (device, u16) = argmin_j
+ * |x - c_j|^2 over codebook[K][D] (float32), evaluated as |c_j|^2 - 2 x.c_j in FP32 on the matrix cores;
+ * equal values go to the smaller index.  half_codebook = 1 measures against the float16 rounding of each
+ * codeword (the stored one).  K in [1, 65536].  Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_vq_assign(const float* x, int32_t D, const uint32_t* rows, int64_t m, const float* codebook, int32_t K,
+                   int32_t half_codebook, uint16_t* code, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes for cgv2_vq_update. */
+size_t cgv2_vq_update_workspace(int32_t K, int32_t D);
+
+/* Lloyd update: every codeword with members becomes their mean (FP64 sums, rounded once), one without
+ * keeps its value; counts[K] (device, u32) receives the member counts.  codebook is read and written.
+ * Errors: CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EHIP. */
+int cgv2_vq_update(const float* x, int32_t D, const uint32_t* rows, int64_t m, const uint16_t* code, int32_t K,
+                   float* codebook, uint32_t* counts, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Destination of cgv2_compact_write: the arrays of cgv2_surfels_compact (float16 as uint16_t bits) for
+ * n = the input's n: mean[3][n], log_scale[2][n], quat[4][n], opacity_logit[n], sh[n][(deg+1)^2][3] (the
+ * first *n_full rows are written), codebook[K][(deg+1)^2][3]. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  float* mean;
+  uint16_t *log_scale, *quat, *opacity_logit, *sh, *codebook;
+} cgv2_compact_out;
+
+/* Writes the stored arrays of s in the slot order of cgv2_compact_order (order, n_full as it left them):
+ * positions copied, everything else rounded to float16 (nearest, ties to even), the SH of the kept slots
+ * and the K codewords of codebook[K][(deg+1)^2][3] (float32; may be NULL with K = 0).  The codes of the
+ * quantized slots are cgv2_vq_assign's output over rows = order + n_full.
+ * Errors: CGV2_EINVAL, CGV2_EHIP. */
+int cgv2_compact_write(const cgv2_surfels* s, const uint32_t* order, const int64_t* n_full, const float* codebook,
+                       int32_t K, const cgv2_compact_out* out, void* hip_stream);
+
 /* Error string for a CGV2_E* code; thread-local hipError_t of the last failing launch. */
 const char* cgv2_strerror(int code);
 int cgv2_last_hip_error(void);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgv2r.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["capi.hip", "project.hip", "binsort.hip", "render.hip", "loss.hip", "densify.hip", "trim.hip", "action.hip", "crop.hip"]
+SOURCES = ["capi.hip", "project.hip", "binsort.hip", "render.hip", "loss.hip", "densify.hip", "trim.hip", "action.hip", "crop.hip", "vq.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
          # packed FP32 (v_pk_*_f32) is kept off: hipcc would otherwise form it from scalar code

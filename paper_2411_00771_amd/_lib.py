@@ -22,7 +22,9 @@ EXPORTS = ["cgv2_project", "cgv2_project_compact", "cgv2_bin_sort_workspace", "c
            "cgv2_densify_stats", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
            "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_densify_plan_workspace", "cgv2_densify_plan",
            "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_visibility_workspace", "cgv2_visibility_count",
-           "cgv2_crop_workspace", "cgv2_crop_volume", "cgv2_strerror", "cgv2_last_hip_error"]
+           "cgv2_crop_workspace", "cgv2_crop_volume", "cgv2_compact_order_workspace", "cgv2_compact_order",
+           "cgv2_vq_init", "cgv2_vq_assign_workspace", "cgv2_vq_assign", "cgv2_vq_update_workspace", "cgv2_vq_update",
+           "cgv2_compact_write", "cgv2_strerror", "cgv2_last_hip_error"]
 
 P = ctypes.c_void_p
 
@@ -42,6 +44,11 @@ class SurfelsCompact(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_full", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
                 ("codebook_size", ctypes.c_int32), ("mean", P), ("log_scale", P), ("quat", P),
                 ("opacity_logit", P), ("sh", P), ("code", P), ("codebook", P)]
+
+
+class CompactOut(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mean", P), ("log_scale", P), ("quat", P),
+                ("opacity_logit", P), ("sh", P), ("codebook", P)]
 
 
 class Proj(ctypes.Structure):
@@ -143,6 +150,14 @@ def lib():
         "cgv2_crop_workspace": (sz, [i64]),
         "cgv2_crop_volume": (ctypes.c_int, [P, i64, P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), P, P, P, P, P,
                                             sz, P]),
+        "cgv2_compact_order_workspace": (sz, [i64]),
+        "cgv2_compact_order": (ctypes.c_int, [P, i64, P, P, P, sz, P]),
+        "cgv2_vq_init": (ctypes.c_int, [P, i32, P, i64, i32, P, P]),
+        "cgv2_vq_assign_workspace": (sz, [i32]),
+        "cgv2_vq_assign": (ctypes.c_int, [P, i32, P, i64, P, i32, i32, P, P, sz, P]),
+        "cgv2_vq_update_workspace": (sz, [i32, i32]),
+        "cgv2_vq_update": (ctypes.c_int, [P, i32, P, i64, P, i32, P, P, P, sz, P]),
+        "cgv2_compact_write": (ctypes.c_int, [ctypes.POINTER(Surfels), P, P, P, i32, ctypes.POINTER(CompactOut), P]),
         "cgv2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cgv2_last_hip_error": (ctypes.c_int, []),
     }

@@ -372,4 +372,55 @@ int cgv2_crop_volume(const float* points, int64_t m, const uint32_t* count, uint
                                      (hipStream_t)stream));
 }
 
+size_t cgv2_compact_order_workspace(int64_t n) { return n < 0 ? 0 : cgv2_part_ws_layout(n); }
+
+int cgv2_compact_order(const uint8_t* quantize, int64_t n, uint32_t* order, int64_t* n_full, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= (int64_t)0xffffffff || !n_full || (n > 0 && (!quantize || !order))) return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_compact_order_workspace(n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_compact_order(quantize, n, order, n_full, workspace, (hipStream_t)stream));
+}
+
+static bool vq_dim_ok(int32_t D) {
+  const int DP = (D + 3) & ~3;
+  return D >= 1 && (DP == 4 || DP == 12 || DP == 28 || DP == 48);
+}
+
+int cgv2_vq_init(const float* x, int32_t D, const uint32_t* rows, int64_t m, int32_t K, float* codebook,
+                 void* stream) {
+  if (!vq_dim_ok(D) || m < 1 || K < 1 || K > 65536 || !x || !rows || !codebook) return CGV2_EINVAL;
+  return hip_status(cgv2_launch_vq_init(x, D, rows, m, K, codebook, (hipStream_t)stream));
+}
+
+size_t cgv2_vq_assign_workspace(int32_t K) { return K < 1 ? 0 : cgv2_vq_assign_ws_layout(K); }
+
+int cgv2_vq_assign(const float* x, int32_t D, const uint32_t* rows, int64_t m, const float* codebook, int32_t K,
+                   int32_t half_codebook, uint16_t* code, void* workspace, size_t ws_bytes, void* stream) {
+  if (!vq_dim_ok(D) || m < 0 || K < 1 || K > 65536 || !codebook || (m > 0 && (!x || !rows || !code)))
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_vq_assign_workspace(K)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_vq_assign(x, D, rows, m, codebook, K, half_codebook ? 1 : 0, code, workspace,
+                                          (hipStream_t)stream));
+}
+
+size_t cgv2_vq_update_workspace(int32_t K, int32_t D) { return (K < 1 || D < 1) ? 0 : cgv2_vq_update_ws_layout(K, D); }
+
+int cgv2_vq_update(const float* x, int32_t D, const uint32_t* rows, int64_t m, const uint16_t* code, int32_t K,
+                   float* codebook, uint32_t* counts, void* workspace, size_t ws_bytes, void* stream) {
+  if (!vq_dim_ok(D) || m < 0 || K < 1 || K > 65536 || !codebook || !counts || (m > 0 && (!x || !rows || !code)))
+    return CGV2_EINVAL;
+  if (!workspace || ws_bytes < cgv2_vq_update_workspace(K, D)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  return hip_status(cgv2_launch_vq_update(x, D, rows, m, code, K, codebook, counts, workspace, (hipStream_t)stream));
+}
+
+int cgv2_compact_write(const cgv2_surfels* s, const uint32_t* order, const int64_t* n_full, const float* codebook,
+                       int32_t K, const cgv2_compact_out* out, void* stream) {
+  if (!surfels_ok(s) || !n_full || !out || out->n != s->n || out->sh_degree != s->sh_degree || K < 0 || K > 65536 ||
+      (K > 0 && (!codebook || !out->codebook)))
+    return CGV2_EINVAL;
+  if (s->n > 0 && (!order || !out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->sh))
+    return CGV2_EINVAL;
+  return hip_status(cgv2_launch_compact_write(*s, order, n_full, codebook, K, *out, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -69,3 +69,18 @@ hipError_t cgv2_launch_vis_count(const float* pts, int64_t m, int V, double rho,
 size_t cgv2_crop_ws_layout(int64_t m, size_t* off);
 hipError_t cgv2_launch_crop(const float* pts, int64_t m, const uint32_t* count, uint32_t tau, const double* T,
                             uint8_t* keep, double* ground, double* hrange, int64_t* kept, void* ws, hipStream_t st);
+
+// serving storage: partition, vector quantization, float16 packing (vq.hip)
+size_t cgv2_part_ws_layout(int64_t n);
+hipError_t cgv2_launch_compact_order(const uint8_t* q, int64_t n, uint32_t* order, int64_t* n_full, void* ws,
+                                     hipStream_t st);
+hipError_t cgv2_launch_vq_init(const float* x, int D, const uint32_t* rows, int64_t m, int K, float* cb,
+                               hipStream_t st);
+size_t cgv2_vq_assign_ws_layout(int K);
+hipError_t cgv2_launch_vq_assign(const float* x, int D, const uint32_t* rows, int64_t m, const float* cb, int K,
+                                 int half_cb, uint16_t* code, void* ws, hipStream_t st);
+size_t cgv2_vq_update_ws_layout(int K, int D);
+hipError_t cgv2_launch_vq_update(const float* x, int D, const uint32_t* rows, int64_t m, const uint16_t* code, int K,
+                                 float* cb, uint32_t* counts, void* ws, hipStream_t st);
+hipError_t cgv2_launch_compact_write(const cgv2_surfels& s, const uint32_t* order, const int64_t* n_full,
+                                     const float* cb, int K, const cgv2_compact_out& out, hipStream_t st);

@@ -190,7 +190,12 @@ class Engine:
         flat = t.view(-1)[: per * width * height]
         return flat.view(per, height, width) if per > 1 else flat.view(height, width)
 
-    def project(self, params: Params, cams):
+    def project(self, params, cams):
+        """Projects a Params or a storage.CompactParams (serving storage) set."""
+        if getattr(params, "is_compact", False):
+            check(_lib.lib().cgv2_project_compact(ctypes.byref(params.struct()), cams, self.V,
+                                                  ctypes.byref(self._proj), _stream()), "cgv2_project_compact")
+            return
         check(_lib.lib().cgv2_project(ctypes.byref(params.struct()), cams, self.V, ctypes.byref(self._proj),
                                       _stream()), "cgv2_project")
 
