@@ -128,6 +128,25 @@ def test_loss_matches_oracle(tiny, cuda):
     assert np.abs(ds - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
 
 
+@pytest.mark.parametrize("W,H", [(150, 37), (64, 16), (65, 17), (1, 1)])
+def test_loss_ragged_multi_view(cuda, W, H):
+    """Loss tiles of 64 x 16 over sizes that leave partial tiles (and a single pixel), two views per call."""
+    import torch
+    from paper_2411_00771_amd import raster
+    rng = np.random.default_rng(W * 100 + H)
+    img = rng.uniform(0, 1, (2, 3, H, W)).astype(np.float32)
+    tgt = rng.uniform(0, 1, (2, 3, H, W)).astype(np.float32)
+    eng = raster.Engine(16, W, H, 2, capacity=1 << 10)
+    lv = eng.loss(torch.from_numpy(tgt).to(cuda), img=torch.from_numpy(img).to(cuda)).cpu().numpy()
+    dt, ds = eng.d_img.cpu().numpy(), eng.d_img_ssim.cpu().numpy()
+    for v in range(2):
+        ref = oracle.ssim_loss(img[v].astype(np.float64), tgt[v])
+        assert abs(lv[v][0] - ref["loss"]) <= 1e-6 * max(1, abs(ref["loss"])) + 2e-7
+        assert abs(lv[v][2] - ref["ssim"]) <= 2e-6
+        assert np.abs(dt[v] - ref["d_total"]).max() <= 1e-4 * np.abs(ref["d_total"]).max()
+        assert np.abs(ds[v] - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
+
+
 def _upstream(tiny, seed=3):
     io = tiny["io"]
     H, W = io["alpha"].shape
