@@ -122,13 +122,20 @@ typedef struct {
  * *status is set to 1 when the intersections exceed 'capacity' (sticky: the library never
  * clears it; the caller zeroes it before the first call).  *needed receives the total number
  * of intersections of the call.  While *status != 0, bins are invalid, render calls write
- * nothing and the caller must rerun with capacity >= *needed. */
+ * nothing and the caller must rerun with capacity >= *needed.
+ * order (optional, [V * tiles]): the render calls' launch order.  When non-NULL, cgv2_bin_sort writes
+ * it and the render calls (forward, count, backward, contribution) launch the tiles of each chunk of up
+ * to 32 views heaviest first: order[32 c tiles + i] = the i-th tile (local index v' tiles + t within
+ * chunk c) by descending log-scale bucket of its list length, ties in index order.  It must come from
+ * the same cgv2_bin_sort call as ranges.  NULL: tiles in spatial order.  Results are the same either
+ * way, up to the summation order of the backward's atomics. */
 typedef struct {
   int64_t capacity;  /* entries in ids (< 2^32 - 1) */
   uint32_t* ids;
   uint32_t* ranges;
   int32_t* status;
   int64_t* needed;
+  uint32_t* order;   /* optional launch order, see above */
 } cgv2_bins;
 
 /* Rendered images [V][c][H][W] and the backward checkpoint.  rgb (Eq. 1, with T_final * bg),

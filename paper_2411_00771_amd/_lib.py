@@ -56,7 +56,7 @@ class Proj(ctypes.Structure):
 
 
 class Bins(ctypes.Structure):
-    _fields_ = [("capacity", ctypes.c_int64), ("ids", P), ("ranges", P), ("status", P), ("needed", P)]
+    _fields_ = [("capacity", ctypes.c_int64), ("ids", P), ("ranges", P), ("status", P), ("needed", P), ("order", P)]
 
 
 class Image(ctypes.Structure):

@@ -371,6 +371,80 @@ __global__ __launch_bounds__(1024) void k_sort_big(const uint32_t* __restrict__ 
   }
 }
 
+// ---- launch order of the render kernels --------------------------------------------------------
+// A render launch holds few tiles per wave slot and tile costs vary by orders of magnitude, so the
+// heaviest tiles go first (longest-processing-time order): a stable counting sort of a view chunk's
+// tiles by a log-scale bucket of their list length, descending, tiles in index order within a bucket.
+constexpr int kOrdBuckets = 64;
+constexpr int kOrdChunk = 1024;  // tiles per workgroup (16 waves)
+
+__device__ __forceinline__ int order_bucket(uint32_t len) {
+  if (len == 0) return 0;
+  const int e = 31 - __clz(len);  // floor(log2 len)
+  const int half = e >= 1 ? (int)((len >> (e - 1)) & 1u) : 0;
+  const int b = 2 * e + 1 + half;
+  return b < kOrdBuckets ? b : kOrdBuckets - 1;
+}
+
+__global__ __launch_bounds__(kOrdChunk) void k_order_hist(const uint32_t* __restrict__ ranges, int64_t base, int T,
+                                                          uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kOrdBuckets];
+  if (threadIdx.x < kOrdBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * kOrdChunk + threadIdx.x;
+  if (t < T) atomicAdd(&h[order_bucket(ranges[base + t + 1] - ranges[base + t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrdBuckets) hist[(int64_t)blockIdx.x * kOrdBuckets + threadIdx.x] = h[threadIdx.x];
+}
+
+// one wave: hist[c][k] -> first slot of bucket k's tiles of chunk c, buckets in descending order
+__global__ __launch_bounds__(64) void k_order_scan(uint32_t* __restrict__ hist, int nc) {
+  const int k = threadIdx.x;  // bucket
+  uint32_t tot = 0;
+  for (int c = 0; c < nc; ++c) tot += hist[(int64_t)c * kOrdBuckets + k];
+  // inclusive suffix sum over the buckets k and above, then exclusive
+  uint32_t x = tot;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_down(x, d, 64);
+    if (k + d < 64) x += y;
+  }
+  uint32_t run = x - tot;
+  for (int c = 0; c < nc; ++c) {
+    const uint32_t v = hist[(int64_t)c * kOrdBuckets + k];
+    hist[(int64_t)c * kOrdBuckets + k] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kOrdChunk) void k_order_place(const uint32_t* __restrict__ ranges, int64_t base, int T,
+                                                           const uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ order) {
+  constexpr int kWaves = kOrdChunk / 64;
+  __shared__ uint32_t wc[kWaves][kOrdBuckets];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * kOrdChunk + threadIdx.x;
+  const int bk = t < T ? order_bucket(ranges[base + t + 1] - ranges[base + t]) : -1;
+  uint32_t rank = 0;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int k = 0; k < kOrdBuckets; ++k) {
+    const unsigned long long msk = __ballot(bk == k);
+    if (bk == k) rank = (uint32_t)__popcll(msk & lt);
+    if (lane == 0) wc[w][k] = (uint32_t)__popcll(msk);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrdBuckets) {
+    uint32_t run = 0;
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t v = wc[q][threadIdx.x];
+      wc[q][threadIdx.x] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  if (bk >= 0) order[hist[(int64_t)blockIdx.x * kOrdBuckets + bk] + wc[w][bk] + rank] = (uint32_t)t;
+}
+
 }  // namespace cgv2
 
 static int64_t scan_blocks(int64_t m) { return (m + cgv2::kScanChunk - 1) / cgv2::kScanChunk; }
@@ -394,6 +468,9 @@ size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, siz
   off[6] = take(8 * (size_t)capacity);
   off[7] = take(4 * (size_t)(vn + 1));
   off[8] = take(8 * (size_t)(scan_blocks(m) + 1));
+  // [9] per-chunk bucket counts of the launch order (one view chunk at a time)
+  const int64_t per = (int64_t)std::min(V, cgv2::kMaxViews) * tiles;
+  off[9] = take(4 * (size_t)cgv2::kOrdBuckets * (size_t)((per + cgv2::kOrdChunk - 1) / cgv2::kOrdChunk + 1));
   return o;
 }
 
@@ -450,5 +527,17 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
                      big_count, b.status);
   hipLaunchKernelGGL(k_sort_big, dim3(256), dim3(1024), 0, st, b.ranges, keys, stk, b.ids, big_list, big_count,
                      b.status);
+  if (b.order) {
+    uint32_t* hist = (uint32_t*)(w + off[9]);
+    for (int v0 = 0; v0 < V; v0 += kMaxViews) {
+      const int T = std::min(V - v0, kMaxViews) * tiles;
+      const int nc = (T + kOrdChunk - 1) / kOrdChunk;
+      const int64_t base = (int64_t)v0 * tiles;
+      hipLaunchKernelGGL(k_order_hist, dim3((unsigned)nc), dim3(kOrdChunk), 0, st, b.ranges, base, T, hist);
+      hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist, nc);
+      hipLaunchKernelGGL(k_order_place, dim3((unsigned)nc), dim3(kOrdChunk), 0, st, b.ranges, base, T, hist,
+                         b.order + base);
+    }
+  }
   return hipGetLastError();
 }

@@ -37,7 +37,18 @@ struct RenderArgs {
   unsigned long long* counters;
   float* cws;   // contribution mode: [V][n] pairs (sum of alpha^gamma T^(1-gamma), pixel count)
   float gamma;
+  const uint32_t* order;  // launch order of this view chunk (heaviest tiles first), or null
 };
+
+// Block -> (local view, tile) index: the bin_sort's heaviest-first order when present (bounded, so a
+// stale order cannot leave the launch), else the XCD-aware spatial mapping.
+__device__ __forceinline__ uint32_t tile_of_block(const RenderArgs& a) {
+  if (a.order) {
+    const uint32_t b = a.order[blockIdx.x];
+    return b < gridDim.x ? b : gridDim.x - 1;
+  }
+  return xcd_remap(blockIdx.x, gridDim.x);
+}
 
 // LDS record, five float4 and the quadrant mask:
 //   q0 = (cx, cy, a11 / sqrt2, a12 / sqrt2)     q1 = (a21 / sqrt2, a22 / sqrt2, w0, w1)
@@ -200,7 +211,7 @@ __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
 template <bool kCount, bool kMask, bool kContrib>
 __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   __shared__ Stage s;
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = tile_of_block(a);
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
@@ -447,7 +458,7 @@ template <bool kGeom>
 __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   __shared__ Stage s;
   const RenderArgs& a = A.r;
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = tile_of_block(a);
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
@@ -575,6 +586,7 @@ static cgv2::RenderArgs make_args(const cgv2_proj& p, const cgv2_bins& b, const 
   a.rec = p.rec;
   a.ids = b.ids;
   a.ranges = b.ranges;
+  a.order = b.order ? b.order + (int64_t)cams.v0 * tiles_x * tiles_y : nullptr;
   a.status = b.status;
   a.cams = cams;
   a.n = n;

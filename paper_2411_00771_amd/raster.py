@@ -132,6 +132,8 @@ class Engine:
         self.visible = torch.empty(vn, dtype=torch.int32, device=device)
         self.visible_start = torch.zeros(V + 1, dtype=torch.int32, device=device)
         self.ranges = torch.zeros(V * self.tiles + 1, dtype=torch.int32, device=device)
+        # render launch order (heaviest tiles first), written by each bin_sort
+        self.order = torch.empty(max(V * self.tiles, 1), dtype=torch.int32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.needed = torch.zeros(1, dtype=torch.int64, device=device)
         self.rgb = torch.empty((V, 3, H, W), device=device)
@@ -163,7 +165,8 @@ class Engine:
         self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
         self.ws_bin = torch.empty(L.cgv2_bin_sort_workspace(self.capacity, self.V, self.tiles, self.n), dtype=torch.uint8,
                                   device=self.device)
-        self._bins = _lib.Bins(self.capacity, ptr(self.ids), ptr(self.ranges), ptr(self.status), ptr(self.needed))
+        self._bins = _lib.Bins(self.capacity, ptr(self.ids), ptr(self.ranges), ptr(self.status), ptr(self.needed),
+                               ptr(self.order))
         # per list entry quadrant-contribution mask written by the forward for the backward
         self.qmask = (torch.empty(max(self.capacity, 1), dtype=torch.uint8, device=self.device)
                       if self.backward_enabled else None)

@@ -147,6 +147,40 @@ def test_loss_ragged_multi_view(cuda, W, H):
         assert np.abs(ds[v] - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
 
 
+def _order_bucket(length):
+    """Log-scale bucket of a list length (two per octave, 64 buckets), as the launch order defines it."""
+    out = np.zeros(length.shape, np.int64)
+    nz = length > 0
+    e = np.floor(np.log2(np.maximum(length, 1))).astype(np.int64)
+    half = np.where(e >= 1, (length >> np.maximum(e - 1, 0)) & 1, 0)
+    out[nz] = np.minimum(2 * e[nz] + 1 + half[nz], 63)
+    return out
+
+
+def test_launch_order_heaviest_first(cuda):
+    """The bins' launch order: per chunk of views, a permutation of the chunk's tiles by descending
+    length bucket, ties in index order; rendering is unchanged by it."""
+    import torch
+    sc = scenes.tiny_scene(5, 3000)
+    cams = [scenes.tiny_camera(200, 150, dist=d) for d in (2.5, 3.0, 3.5)]
+    eng, _, cs = gpu_forward(sc, cams, capacity=1 << 17)
+    torch.cuda.synchronize()
+    T = eng.tiles
+    ranges = eng.ranges.cpu().numpy().view(np.uint32).astype(np.int64)[: 3 * T + 1]
+    order = eng.order.cpu().numpy().view(np.uint32).astype(np.int64)[: 3 * T]
+    length = ranges[1:] - ranges[:-1]
+    bk = _order_bucket(length)
+    ref = np.lexsort((np.arange(3 * T), -bk))
+    assert np.array_equal(order, ref)
+    assert len(np.unique(bk)) > 3
+    # the same images without the order
+    img = eng.rgb.clone()
+    eng._bins.order = None
+    eng.render(cs)
+    torch.cuda.synchronize()
+    assert torch.equal(img, eng.rgb)
+
+
 def _upstream(tiny, seed=3):
     io = tiny["io"]
     H, W = io["alpha"].shape
