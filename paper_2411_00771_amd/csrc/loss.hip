@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ img,
                                                   double* __restrict__ partial) {
   __shared__ float sx[kSide][kSide], sy[kSide][kSide];
   __shared__ float hs[5][kSide][kTile];
-  __shared__ double red[2][256];
+  __shared__ double red[2][4];
   int bx, by, vc;  // vc = v * 3 + channel
   if (!loss_tile(lg, bx, by, vc)) return;
   const int64_t HW = (int64_t)W * H;
@@ -101,20 +101,21 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ img,
     m_sum = m;
     l1_sum = fabsf(sx[ly + kR][lx + kR] - sy[ly + kR][lx + kR]);
   }
-  red[0][threadIdx.x] = m_sum;
-  red[1][threadIdx.x] = l1_sum;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + off];
-      red[1][threadIdx.x] += red[1][threadIdx.x + off];
-    }
-    __syncthreads();
+  // per-block sums in FP64, fixed order: butterfly within each wave, then the four waves in order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m_sum += __shfl_xor(m_sum, o, 64);
+    l1_sum += __shfl_xor(l1_sum, o, 64);
   }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = m_sum;
+    red[1][threadIdx.x >> 6] = l1_sum;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     const int64_t blk = ((int64_t)vc * lg.ty + by) * lg.tx + bx;
-    partial[2 * blk] = red[0][0];
-    partial[2 * blk + 1] = red[1][0];
+    partial[2 * blk] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    partial[2 * blk + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
 }
 

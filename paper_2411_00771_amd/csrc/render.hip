@@ -38,17 +38,24 @@ struct RenderArgs {
   float* cws;   // contribution mode: [V][n] pairs (sum of alpha^gamma T^(1-gamma), pixel count)
   float gamma;
   const uint32_t* order;  // launch order of this view chunk (heaviest tiles first), or null
+  uint32_t n_split;       // the first n_split tiles of 'order' run as four quadrant blocks each
 };
 
 // Block -> (local view, tile) index: the bin_sort's heaviest-first order when present (bounded, so a
 // stale order cannot leave the launch), else the XCD-aware spatial mapping.
+// With a split prefix the launch has 3 n_split extra blocks: blocks [0, 4 n_split) are the quadrant blocks
+// of the n_split heaviest tiles (tile order[i >> 2], quadrant i & 3), the rest run whole tiles.
 __device__ __forceinline__ uint32_t tile_of_block(const RenderArgs& a) {
+  const uint32_t tiles = gridDim.x - 3u * a.n_split;
   if (a.order) {
-    const uint32_t b = a.order[blockIdx.x];
-    return b < gridDim.x ? b : gridDim.x - 1;
+    const uint32_t i = blockIdx.x < 4u * a.n_split ? blockIdx.x >> 2 : blockIdx.x - 3u * a.n_split;
+    const uint32_t b = a.order[i];
+    return b < tiles ? b : tiles - 1u;
   }
-  return xcd_remap(blockIdx.x, gridDim.x);
+  return xcd_remap(blockIdx.x, tiles);
 }
+
+__device__ __forceinline__ bool quadrant_block(const RenderArgs& a) { return blockIdx.x < 4u * a.n_split; }
 
 // LDS record, five float4 and the quadrant mask:
 //   q0 = (cx, cy, a11 / sqrt2, a12 / sqrt2)     q1 = (a21 / sqrt2, a22 / sqrt2, w0, w1)
@@ -205,6 +212,111 @@ __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
 
 // kCount: instead of images, count the (pixel, list entry) pairs of the method (every entry a running
 // pixel meets, quadrant mask or not), the contributing pairs, and the pairs the reverse walks.
+// Forward of one 8x8 quadrant q of a heavy tile (one pixel per lane).  Same arithmetic and decisions as the
+// whole-tile path's quadrant q; the reverse pass's quadrant bit
+// goes into img.qmask by an atomic OR on the entry's word (the four quadrant blocks share the byte,
+// which is cleared before the launch).
+template <bool kCount, bool kMask, bool kContrib, int q>
+__device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& s, uint32_t b) {
+  const int lv = (int)(b / (uint32_t)a.tiles);
+  const int v = a.cams.v0 + lv;
+  const int t = (int)(b % (uint32_t)a.tiles);
+  const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+  const DevCam& c = a.cams.c[lv];
+  const int W = c.W, H = c.H;
+  const int lane = threadIdx.x;
+  const int lx = (lane & 7) + 8 * (q & 1), ly = (lane >> 3) + 8 * (q >> 1);
+  const int ox = tx * kTile, oy = ty * kTile;
+  const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
+  const int64_t vn = (int64_t)v * a.n;
+  const int px = ox + lx, py = oy + ly;
+  const bool in = px < W && py < H;
+  FwdState f;
+  f.T = in ? 1.f : -1.f;
+  f.D = f.Dm = 0.f;
+  f.last = start;
+  f.med = 0xffffffffu;
+  f.C[0] = f.C[1] = f.C[2] = 0.f;
+  f.N[0] = f.N[1] = f.N[2] = 0.f;
+  unsigned long long n_eval = 0, n_con = 0;
+  // lane terms at the quadrant-0 pixel and the quadrant's offset applied by eval_px<q>: the arithmetic of
+  // the whole-tile path, so both paths (and the reverse pass) take bit-identical decisions
+  const float lx0 = (float)(lane & 7) + 0.5f, ly0 = (float)(lane >> 3) + 0.5f;
+  bool live = __ballot(f.T > 0.f) != 0;
+  for (uint32_t base = start; base < end && live; base += 64) {
+    const uint32_t idx = base + lane;
+    if (idx < end) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0);
+    __syncthreads();
+    const int cnt = (int)min(64u, end - base);
+    int reached = cnt;
+    uint64_t cqq = 0;
+    for (int j = 0; j < cnt; ++j) {
+      if (kCount) n_eval += f.T > 0.f ? 1u : 0u;
+      if ((uniform(s.qm[j]) >> q) & 1u) {
+        const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
+        LaneTerms lt;
+        lane_terms(lx0, ly0, q0, q1, q2, lt);
+        Px e;
+        eval_px<q>(lt, q2.y, e);
+        float csum = 0.f, ccnt = 0.f;
+        if (fwd_px<kContrib>(e, q2, q3, q4, base + (uint32_t)j, f, n_con, a.gamma, csum, ccnt)) {
+          if (kMask) cqq |= 1ull << j;
+          if (kContrib) {
+            const float ts = wave_sum_lane63(csum), tc = wave_sum_lane63(ccnt);
+            if (lane == 63 && tc > 0.f) {
+              float* w = a.cws + 2 * (vn + (int64_t)__float_as_uint(q3.w));
+              atomicAdd(w, ts);
+              atomicAdd(w + 1, tc);
+            }
+          }
+        }
+      }
+      if ((j & 15) == 15 && __ballot(f.T > 0.f) == 0) {
+        reached = j + 1;
+        break;
+      }
+    }
+    if (kMask && lane < reached && ((cqq >> lane) & 1u)) {
+      uint32_t* word = (uint32_t*)(a.img.qmask + (idx & ~3u));
+      atomicOr(word, 1u << (8u * (idx & 3u) + (uint32_t)q));
+    }
+    live = __ballot(f.T > 0.f) != 0;
+    __syncthreads();
+  }
+  if (kContrib) return;
+  if (kCount) {
+    const unsigned long long n_bwd = in ? f.last - start : 0u;
+    atomicAdd(a.counters + 0, n_eval);
+    atomicAdd(a.counters + 1, n_con);
+    atomicAdd(a.counters + 2, n_bwd);
+    return;
+  }
+  if (!in) return;
+  const int64_t HW = (int64_t)W * H;
+  const cgv2_image& im = a.img;
+  const int64_t p = (int64_t)py * W + px;
+  const float T = fabsf(f.T);
+  if (im.rgb) {
+    float* o = im.rgb + (int64_t)v * 3 * HW + p;
+    o[0] = fmaf(T, c.bg[0], f.C[0]);
+    o[HW] = fmaf(T, c.bg[1], f.C[1]);
+    o[2 * HW] = fmaf(T, c.bg[2], f.C[2]);
+  }
+  if (im.normal) {
+    float* o = im.normal + (int64_t)v * 3 * HW + p;
+    o[0] = f.N[0];
+    o[HW] = f.N[1];
+    o[2 * HW] = f.N[2];
+  }
+  const int64_t vp = (int64_t)v * HW + p;
+  if (im.depth) im.depth[vp] = f.D;
+  if (im.depth_med) im.depth_med[vp] = f.Dm;
+  if (im.alpha) im.alpha[vp] = 1.f - T;
+  if (im.T_final) im.T_final[vp] = T;
+  if (im.last) im.last[vp] = f.last;
+  if (im.med) im.med[vp] = f.med;
+}
+
 // kMask: also write the per-entry quadrant mask img.qmask for the reverse pass.
 // kContrib: instead of images, add each surfel's contribution sums (Sec. 3.3, Eq. 3) of this view into
 // a.cws, one wave reduction and one atomic pair per (surfel, tile).
@@ -212,10 +324,19 @@ template <bool kCount, bool kMask, bool kContrib>
 __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   __shared__ Stage s;
   const uint32_t b = tile_of_block(a);
+  if (*a.status != 0) return;
+  if (quadrant_block(a)) {
+    switch (blockIdx.x & 3u) {
+      case 0: render_fwd_quadrant<kCount, kMask, kContrib, 0>(a, s, b); break;
+      case 1: render_fwd_quadrant<kCount, kMask, kContrib, 1>(a, s, b); break;
+      case 2: render_fwd_quadrant<kCount, kMask, kContrib, 2>(a, s, b); break;
+      default: render_fwd_quadrant<kCount, kMask, kContrib, 3>(a, s, b); break;
+    }
+    return;
+  }
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
-  if (*a.status != 0) return;
   const int tx = t % a.tiles_x, ty = t / a.tiles_x;
   const DevCam& c = a.cams.c[lv];
   const int W = c.W, H = c.H;
@@ -452,6 +573,95 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
   acc[G_SCY] -= dsy;
 }
 
+// Reverse pass over one 8x8 quadrant q of a heavy tile (one pixel per lane): the whole-tile path's
+// quadrant q (same arithmetic and decisions), with its record gradients added per (surfel, quadrant).
+template <bool kGeom, int q>
+__device__ __forceinline__ void render_bwd_quadrant(const BwdArgs& A, Stage& s, uint32_t b) {
+  const RenderArgs& a = A.r;
+  const int lv = (int)(b / (uint32_t)a.tiles);
+  const int v = a.cams.v0 + lv;
+  const int t = (int)(b % (uint32_t)a.tiles);
+  const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+  const DevCam& c = a.cams.c[lv];
+  const int W = c.W, H = c.H;
+  const int lane = threadIdx.x;
+  const int ox = tx * kTile, oy = ty * kTile;
+  const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
+  const int64_t vn = (int64_t)v * a.n;
+  const int64_t HW = (int64_t)W * H;
+  float* rgv = A.rg.row + (int64_t)v * a.n * kGradRow;
+  float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
+  BwdState p;
+  {
+    const int px = ox + (lane & 7) + 8 * (q & 1), py = oy + (lane >> 3) + 8 * (q >> 1);
+    const bool in = px < W && py < H;
+    const int64_t pp = in ? (int64_t)py * W + px : 0;
+    const int64_t vp = (int64_t)v * HW + pp;
+    const int64_t v3 = (int64_t)v * 3 * HW + pp;
+    p.last = in ? min(max(a.img.last[vp], start), end) : start;
+    p.med = in ? a.img.med[vp] : 0xffffffffu;
+    p.Tf = in ? a.img.T_final[vp] : 1.f;
+    p.T = p.Tf;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      p.GC[ch] = in ? ldg0(A.up.d_rgb, v3 + ch * HW) : 0.f;
+      p.GS[ch] = in ? ldg0(A.up.d_rgb_ssim, v3 + ch * HW) : 0.f;
+      p.GN[ch] = kGeom && in ? ldg0(A.up.d_normal, v3 + ch * HW) : 0.f;
+      p.SC[ch] = p.Tf * c.bg[ch];
+      p.SN[ch] = 0.f;
+    }
+    p.GD = kGeom && in ? ldg0(A.up.d_depth, vp) : 0.f;
+    p.GM = kGeom && in ? ldg0(A.up.d_depth_med, vp) : 0.f;
+    p.GA = kGeom && in ? ldg0(A.up.d_alpha, vp) : 0.f;
+    p.SD = 0.f;
+  }
+  uint32_t h = p.last;
+  for (int off = 1; off < 64; off <<= 1) h = max(h, __shfl_xor(h, off));
+  const uint32_t hi = uniform(h);
+  const float lx0 = (float)(lane & 7) + 0.5f, ly0 = (float)(lane >> 3) + 0.5f;
+  for (uint32_t top = hi; top > start;) {
+    const uint32_t lo = top - start > 64u ? top - 64u : start;
+    const uint32_t idx = lo + lane;
+    if (idx < top) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx);
+    __syncthreads();
+    for (int j = (int)(top - lo) - 1; j >= 0; --j) {
+      if (!((uniform(s.qm[j]) >> q) & 1u)) continue;
+      const uint32_t e_idx = lo + (uint32_t)j;
+      const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
+      LaneTerms lt;
+      lane_terms(lx0, ly0, q0, q1, q2, lt);
+      float acc[kGradFields];
+#pragma unroll
+      for (int f = 0; f < kGradFields; ++f) acc[f] = 0.f;
+      bool any = false;
+      bwd_px<q, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p, acc, any);
+      if (__ballot(any) == 0) continue;
+      float red[16];
+#pragma unroll
+      for (int f = 0; f < 16; ++f) red[f] = acc[f];
+      const float tot = reduce16_scatter(red);
+      const int slot = reduce16_index(lane);
+      const uint32_t id = __float_as_uint(q3.w);
+      if ((lane & 12) == 0 && (kGeom || slot != G_ZC)) {
+        const bool anum = slot >= G_A11 && slot <= G_A22;
+        atomicAdd(rgv + (int64_t)id * kGradRow + slot, anum ? tot * kInvSqrt2 : tot);
+      }
+      if (kGeom) {
+        const float nx = wave_sum_lane63(acc[G_NX]), ny = wave_sum_lane63(acc[G_NY]),
+                    nz = wave_sum_lane63(acc[G_NZ]);
+        if (lane == 63) {
+          float* w = rgn + (int64_t)id * kGradNrm;
+          atomicAdd(w, nx);
+          atomicAdd(w + 1, ny);
+          atomicAdd(w + 2, nz);
+        }
+      }
+    }
+    __syncthreads();
+    top = lo;
+  }
+}
+
 // kGeom: depth, median-depth, normal or alpha upstream gradients are present.  Without them (the
 // photometric-loss-only case) their per-pixel state, terms and four of the reductions drop out.
 template <bool kGeom>
@@ -459,10 +669,19 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   __shared__ Stage s;
   const RenderArgs& a = A.r;
   const uint32_t b = tile_of_block(a);
+  if (*a.status != 0) return;
+  if (quadrant_block(a)) {
+    switch (blockIdx.x & 3u) {
+      case 0: render_bwd_quadrant<kGeom, 0>(A, s, b); break;
+      case 1: render_bwd_quadrant<kGeom, 1>(A, s, b); break;
+      case 2: render_bwd_quadrant<kGeom, 2>(A, s, b); break;
+      default: render_bwd_quadrant<kGeom, 3>(A, s, b); break;
+    }
+    return;
+  }
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
-  if (*a.status != 0) return;
   const int tx = t % a.tiles_x, ty = t / a.tiles_x;
   const DevCam& c = a.cams.c[lv];
   const int W = c.W, H = c.H;
@@ -580,6 +799,26 @@ __global__ __launch_bounds__(256) void k_zero_visible(const uint32_t* __restrict
 
 }  // namespace cgv2
 
+// Heavy tiles split into quadrant blocks: 1 / kSplitDiv of a launch's tiles, at most kSplitMax.
+#ifndef CGV2_SPLIT_DIV
+#define CGV2_SPLIT_DIV 16
+#endif
+constexpr int kSplitDiv = CGV2_SPLIT_DIV;
+constexpr int kSplitMax = 1024;
+
+namespace cgv2 {
+// Clears the quadrant-mask bytes of the split tiles' lists (their four quadrant blocks OR their bits in).
+__global__ __launch_bounds__(256) void k_clear_split_qmask(RenderArgs a) {
+  if (*a.status != 0) return;  // overflowed bins: ranges may lie beyond the list arrays
+  const uint32_t tiles = (uint32_t)a.cams.count * (uint32_t)a.tiles;
+  const uint32_t b0 = a.order[blockIdx.x];
+  const uint32_t b = b0 < tiles ? b0 : tiles - 1u;
+  const int v = a.cams.v0 + (int)(b / (uint32_t)a.tiles), t = (int)(b % (uint32_t)a.tiles);
+  const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
+  for (uint32_t e = start + threadIdx.x; e < end; e += blockDim.x) a.img.qmask[e] = 0;
+}
+}  // namespace cgv2
+
 static cgv2::RenderArgs make_args(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                   int tiles_x, int tiles_y, const cgv2_image* img, unsigned long long* counters) {
   cgv2::RenderArgs a;
@@ -597,13 +836,16 @@ static cgv2::RenderArgs make_args(const cgv2_proj& p, const cgv2_bins& b, const 
   a.counters = counters;
   a.cws = nullptr;
   a.gamma = 0.f;
+  a.n_split = a.order ? (uint32_t)std::min<int64_t>((int64_t)cams.count * a.tiles / kSplitDiv, kSplitMax) : 0u;
   return a;
 }
 
 hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                   int tiles_x, int tiles_y, const cgv2_image& img, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
+  if (img.qmask && a.n_split)
+    hipLaunchKernelGGL(cgv2::k_clear_split_qmask, dim3(a.n_split), dim3(256), 0, st, a);
   if (img.qmask) hipLaunchKernelGGL((cgv2::k_render_fwd<false, true, false>), dim3(grid), dim3(64), 0, st, a);
   else hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
@@ -612,7 +854,7 @@ hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const 
 hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                     int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, counters);
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
   hipLaunchKernelGGL((cgv2::k_render_fwd<true, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
@@ -629,7 +871,7 @@ hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const 
   A.r = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
   A.up = up;
   A.rg = rg;
-  const unsigned grid = (unsigned)((int64_t)cams.count * A.r.tiles);
+  const unsigned grid = (unsigned)((int64_t)cams.count * A.r.tiles + 3 * A.r.n_split);
   const bool geom = up.d_depth || up.d_depth_med || up.d_normal || up.d_alpha;
   if (geom) hipLaunchKernelGGL(cgv2::k_render_bwd<true>, dim3(grid), dim3(64), 0, st, A);
   else hipLaunchKernelGGL(cgv2::k_render_bwd<false>, dim3(grid), dim3(64), 0, st, A);
@@ -641,7 +883,7 @@ hipError_t cgv2_launch_contribution(const cgv2_proj& p, const cgv2_bins& b, cons
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, nullptr);
   a.cws = cws;
   a.gamma = gamma;
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
   hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, true>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
