@@ -414,6 +414,9 @@ class Rasterize2DGS(torch.autograd.Function):
                         sh_degree)
         engine.forward(params, cams)
         ctx.engine, ctx.cams, ctx.params = engine, cams, params
+        # outputs the loss does not use reach the backward as None, not as zero images: the reverse
+        # pass then skips the depth / normal / alpha terms entirely
+        ctx.set_materialize_grads(False)
         return engine.rgb, engine.depth, engine.depth_med, engine.normal, engine.alpha
 
     @staticmethod

@@ -39,11 +39,21 @@ def _autograd_grads(sc, cams, targets, cuda):
     ts = [torch.from_numpy(getattr(sc, k)).to(cuda).requires_grad_(True)
           for k in ("mean", "log_scale", "quat", "opacity_logit")]
     ts.append(torch.from_numpy(np.ascontiguousarray(sc.sh.transpose(2, 0, 1))).to(cuda).requires_grad_(True))
+    seen = []
+    orig = eng.backward
+
+    def spy(*a, **kw):
+        seen.append(sorted(k for k, v in kw.items() if v is not None))
+        return orig(*a, **kw)
+
+    eng.backward = spy
     rgb, depth, dmed, normal, alpha = raster.rasterize(ts, eng, cs, sc.sh_degree)
     loss = raster.L1SSIMLoss.apply(rgb, torch.from_numpy(np.stack(targets)).to(cuda), eng, 0.2)
     loss.backward()
     torch.cuda.synchronize()
     assert eng.status.item() == 0
+    # only the colour terms reach the reverse pass (unused outputs are not materialized as zeros)
+    assert seen == [["d_rgb", "d_rgb_ssim"]]
     grads = [t.grad.cpu().numpy() for t in ts[:4]] + [raster.Params.sh_planar(ts[4].grad)]
     return eng, grads, loss.item()
 
