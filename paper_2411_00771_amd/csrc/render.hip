@@ -6,10 +6,10 @@
 // list are staged 64 at a time into LDS (one per lane, as five float4), converting the centre to
 // tile-relative coordinates exactly ((cx_hi - tile_x0) + cx_lo), pre-scaling the homography
 // numerator by 1/sqrt(2) (so rho/2 comes out directly), replacing the opacity by log2(o) and 1/o,
-// and reducing the surfel's pixel rect to a 4-bit mask of the quadrants it reaches.  The rect holds
-// every pixel at which the surfel can reach alpha >= 1/255, so a quadrant outside it is skipped
-// wave-uniformly, as is a quadrant whose pixels have all stopped; within a quadrant the evaluation is
-// branch-free, and the homography terms of a lane's four pixels are one add apart.
+// and reducing the surfel's pixel rect to a 4-bit mask of the quadrants it reaches, less those its
+// alpha >= 1/255 region (an ellipse, plus the screen-filter disc) misses.  A quadrant outside the mask
+// is skipped wave-uniformly, as is a quadrant whose pixels have all stopped; within a quadrant the
+// evaluation is branch-free, and the homography terms of a lane's four pixels are one add apart.
 //
 // The reverse walks each pixel's list from its checkpointed 'last' entry downwards, recovers T by
 // division, sums the per-surfel gradients of its four pixels in registers, reduces them over the
@@ -65,7 +65,58 @@ struct Stage {
   uint32_t qm[64];
 };
 
-// qmask (optional): the forward's per-entry mask of quadrants with a contributing pixel, ANDed in.
+// Quadrants (bits of 'm') in which some pixel sample can reach alpha >= 1/255.  rho is the smaller of
+// the ray-splat distance |A x|^2 / w(x)^2 and the screen-filter distance |x|^2 (x relative to the
+// projected centre; A, w as staged, so this is the function the evaluation rounds), and the cutoff is
+// rho <= c = ln(255 o) = k2 / 2.  {|A x|^2 <= c w(x)^2} is the conic g(x) = x'Gx + 2 b'x + d <= 0; when
+// G is positive definite it is an ellipse, met by a box iff its centre lies inside the box or the
+// minimum of g over one of the four edges is <= 0.  FP64 throughout, with the cutoff enlarged by
+// 2e-3 relative + 1e-3 and the box by 1/64 px, far beyond the FP32 error of the evaluation, so a
+// quadrant is dropped only where no pixel can take the surfel.  A conic that is not an ellipse keeps
+// the rect's quadrants.
+__device__ __forceinline__ uint32_t reach_quadrants(uint32_t m, float cxt, float cyt, float a11, float a12, float a21,
+                                                    float a22, float w0f, float w1f, float w2f, float k2) {
+  const double c = 0.5 * (double)k2 * (1.0 + 2e-3) + 1e-3;
+  const double A11 = a11, A12 = a12, A21 = a21, A22 = a22, w0 = w0f, w1 = w1f, w2 = w2f;
+  const double G00 = A11 * A11 + A21 * A21 - c * w1 * w1;
+  const double G01 = A11 * A12 + A21 * A22 - c * w1 * w2;
+  const double G11 = A12 * A12 + A22 * A22 - c * w2 * w2;
+  const double det = G00 * G11 - G01 * G01;
+  const bool ellipse = G00 > 0.0 && G11 > 0.0 && det > 0.0;
+  const double b0 = -c * w0 * w1, b1 = -c * w0 * w2, d = -c * w0 * w0;
+  const double i00 = ellipse ? 1.0 / G00 : 0.0, i11 = ellipse ? 1.0 / G11 : 0.0, idet = ellipse ? 1.0 / det : 0.0;
+  const double xs = -(G11 * b0 - G01 * b1) * idet, ys = -(G00 * b1 - G01 * b0) * idet;
+  auto g = [&](double x, double y) {
+    return fma(G00 * x, x, fma(2.0 * G01 * x, y, fma(G11 * y, y, fma(2.0 * b0, x, fma(2.0 * b1, y, d)))));
+  };
+  constexpr double kPad = 1.0 / 64.0;
+  uint32_t out = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!((m >> k) & 1u)) continue;
+    const double xl = (double)(8 * (k & 1)) + 0.5 - (double)cxt - kPad, xh = xl + 7.0 + 2.0 * kPad;
+    const double yl = (double)(8 * (k >> 1)) + 0.5 - (double)cyt - kPad, yh = yl + 7.0 + 2.0 * kPad;
+    // screen-filter disc |x|^2 <= c
+    const double dx = xl > 0.0 ? xl : (xh < 0.0 ? xh : 0.0), dy = yl > 0.0 ? yl : (yh < 0.0 ? yh : 0.0);
+    bool hit = dx * dx + dy * dy <= c;
+    if (!hit) {
+      if (!ellipse || (xs >= xl && xs <= xh && ys >= yl && ys <= yh)) {
+        hit = true;
+      } else {
+        const double yA = fmin(fmax(-(G01 * xl + b1) * i11, yl), yh);
+        const double yB = fmin(fmax(-(G01 * xh + b1) * i11, yl), yh);
+        const double xA = fmin(fmax(-(G01 * yl + b0) * i00, xl), xh);
+        const double xB = fmin(fmax(-(G01 * yh + b0) * i00, xl), xh);
+        hit = fmin(fmin(g(xl, yA), g(xh, yB)), fmin(g(xA, yl), g(xB, yh))) <= 0.0;
+      }
+    }
+    out |= hit ? 1u << k : 0u;
+  }
+  return out;
+}
+
+// qmask (optional): the forward's per-entry mask of quadrants with a contributing pixel, ANDed in;
+// without it the quadrants the surfel cannot reach are dropped by reach_quadrants.
 __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* rec, int64_t vn, int64_t n, uint32_t id,
                                              int ox, int oy, const uint8_t* qmask, uint32_t idx) {
   // an id outside [0, n) (never produced by the binning) stages a record that reaches no quadrant
@@ -73,8 +124,10 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
   const float4* r = (const float4*)(rec + (size_t)(vn + (valid ? id : 0u)) * kRec);
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
   const float fox = (float)ox, foy = (float)oy;
-  s.q[lane][0] = make_float4((r0.x - fox) + r0.z, (r0.y - foy) + r0.w, r1.x * kInvSqrt2, r1.y * kInvSqrt2);
-  s.q[lane][1] = make_float4(r1.z * kInvSqrt2, r1.w * kInvSqrt2, r2.x, r2.y);
+  const float4 q0 = make_float4((r0.x - fox) + r0.z, (r0.y - foy) + r0.w, r1.x * kInvSqrt2, r1.y * kInvSqrt2);
+  const float4 q1 = make_float4(r1.z * kInvSqrt2, r1.w * kInvSqrt2, r2.x, r2.y);
+  s.q[lane][0] = q0;
+  s.q[lane][1] = q1;
   s.q[lane][2] = make_float4(r2.z, valid ? log2f(r3.x) : -INFINITY, r2.w, r2.w * r2.x);
   s.q[lane][3] = make_float4(r3.y, r3.z, r3.w, __uint_as_float(valid ? id : 0u));
   s.q[lane][4] = make_float4(r4.x, r4.y, r4.z, valid ? 1.f / r3.x : 0.f);
@@ -89,6 +142,7 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
     if (i0 <= x0 + 7 && i1 >= x0 && j0 <= y0 + 7 && j1 >= y0) m |= 1u << k;
   }
   if (qmask) m &= qmask[idx];
+  else if (m) m = reach_quadrants(m, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r2.z, r4.w);
   s.qm[lane] = valid ? m : 0u;
 }
 
