@@ -95,19 +95,64 @@ def project(scene, cam):
     return out
 
 
-def bin_tiles(tile_rect, depth32, width, height):
-    """Per-tile lists ordered by (float32 depth bits, id)."""
+def bin_tiles(tile_rect, depth32, width, height, keep=None):
+    """Per-tile lists ordered by (float32 depth bits, id): every tile of each surfel's tile rect, or,
+    with ``keep`` (one byte per rect tile in the order of :func:`rect_tiles`), those it marks."""
     tile_rect = np.ascontiguousarray(tile_rect, np.int32)
     depth32 = np.ascontiguousarray(depth32, np.float32)
+    keep = None if keep is None else np.ascontiguousarray(keep, np.uint8)
     n = tile_rect.shape[0]
     ntiles = ((width + 15) // 16) * ((height + 15) // 16)
     offsets = np.zeros(ntiles + 1, np.int64)
     L = lib()
     L.orc_bin.restype = ctypes.c_int64
-    K = L.orc_bin(ctypes.c_int64(n), width, height, _p(tile_rect), _p(depth32), _p(offsets), None, ctypes.c_int64(0))
+    K = L.orc_bin(ctypes.c_int64(n), width, height, _p(tile_rect), _p(depth32), _p(keep), _p(offsets), None,
+                  ctypes.c_int64(0))
     ids = np.zeros(max(K, 1), np.int32)
-    L.orc_bin(ctypes.c_int64(n), width, height, _p(tile_rect), _p(depth32), _p(offsets), _p(ids), ctypes.c_int64(K))
+    L.orc_bin(ctypes.c_int64(n), width, height, _p(tile_rect), _p(depth32), _p(keep), _p(offsets), _p(ids),
+              ctypes.c_int64(K))
     return offsets, ids[:K]
+
+
+def rect_tiles(tile_rect, width):
+    """(surfel, tile) of every tile of every surfel's tile rect, in (surfel, row, column) order."""
+    r = np.asarray(tile_rect, np.int64)
+    w = np.maximum(r[:, 2] - r[:, 0], 0)
+    h = np.maximum(r[:, 3] - r[:, 1], 0)
+    cnt = w * h
+    sid = np.repeat(np.arange(r.shape[0]), cnt)
+    k = np.arange(int(cnt.sum())) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    tx = r[sid, 0] + k % np.maximum(w[sid], 1)
+    ty = r[sid, 1] + k // np.maximum(w[sid], 1)
+    return sid, ty * ((width + 15) // 16) + tx
+
+
+def tile_reach(proj):
+    """The list rule: which tiles of each surfel's tile rect its cutoff region rho <= k2 can reach
+    (evaluated with k2 enlarged by 2e-3 relative + 2e-3 and the tile's pixel-sample box padded by
+    1/64 px), and which of these decisions are fragile (flip when the enlarged cutoff moves by 1e-5
+    relative and the pad by 1e-3 px).  Arrays over the rect tiles in :func:`rect_tiles` order."""
+    tr = np.ascontiguousarray(proj["tile_rect"], np.int32)
+    n = tr.shape[0]
+    L = lib()
+    L.orc_tile_reach.restype = ctypes.c_int64
+    M, k2 = _d(proj["M"]), _d(proj["k2"])
+    total = L.orc_tile_reach(ctypes.c_int64(n), _p(M), _p(k2), _p(tr), None, None)
+    keep = np.zeros(max(total, 1), np.uint8)
+    fragile = np.zeros(max(total, 1), np.uint8)
+    L.orc_tile_reach(ctypes.c_int64(n), _p(M), _p(k2), _p(tr), _p(keep), _p(fragile))
+    return keep[:total].astype(bool), fragile[:total].astype(bool)
+
+
+def bin_view(proj, cam):
+    """Per-tile lists of one view under the list rule of :func:`tile_reach`.  Returns (offsets, ids,
+    info) with info = dict(rect_total: entries of the plain tile-rect lists, fragile: int64 keys
+    tile * n + surfel of the fragile (tile, surfel) decisions)."""
+    keep, fragile = tile_reach(proj)
+    offsets, ids = bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height, keep=keep)
+    sid, tile = rect_tiles(proj["tile_rect"], cam.width)
+    n = proj["tile_rect"].shape[0]
+    return offsets, ids, dict(rect_total=int(keep.size), fragile=tile[fragile] * n + sid[fragile])
 
 
 # ---------------------------------------------------------------------------------------------
@@ -179,13 +224,15 @@ def contribution(proj, cam, offsets, ids, gamma=0.5, fragile=-1.0):
     """Per-surfel contribution in one view, Sec. 3.3 Eq. 3: C = (1/|P|) sum_P alpha^gamma T^(1-gamma) over
     the pixels P where the surfel is blended (T = transmittance in front of it); C = 0 when P is empty.
     'fragile' counts, per surfel, the pixels where it is evaluated and whose decision margin is below the
-    given bound (each can move its count by at most 1 and its sum by at most one term)."""
+    given bound (each can move its count by at most 1 and its sum by at most one term); 'err' bounds, to
+    first order, the error an FP32 evaluation of the terms makes in 'sum' (FP32 error model of alpha and
+    of the accumulated T, as behind the decision margins)."""
     n = proj["M"].shape[0]
-    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64), fragile=np.zeros(n, np.int32))
+    out = dict(sum=np.zeros(n), cnt=np.zeros(n, np.int64), fragile=np.zeros(n, np.int32), err=np.zeros(n))
     lib().orc_contribution(ctypes.c_int64(n), _p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]),
                            _p(proj["opacity"]), _p(_d(cam.as_array())), _p(np.ascontiguousarray(offsets, np.int64)),
                            _p(np.ascontiguousarray(ids, np.int32)), ctypes.c_double(gamma), ctypes.c_double(fragile),
-                           _p(out["sum"]), _p(out["cnt"]), _p(out["fragile"]))
+                           _p(out["sum"]), _p(out["cnt"]), _p(out["fragile"]), _p(out["err"]))
     out["C"] = np.where(out["cnt"] > 0, out["sum"] / np.maximum(out["cnt"], 1), 0.0)
     return out
 
@@ -384,7 +431,7 @@ def new_densify_state(n):
 
 def forward_view(scene, cam):
     proj = project(scene, cam)
-    offsets, ids = bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height)
+    offsets, ids, _ = bin_view(proj, cam)
     img = render(proj, cam, offsets, ids)
     return proj, offsets, ids, img
 

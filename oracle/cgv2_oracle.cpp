@@ -10,6 +10,7 @@
 //   orc_project      surfel parameters -> per-view screen transform M = K [R s_u t_u | R s_v t_v | R mu + t],
 //                    SH colour, camera-facing normal, opacity, exact conic bounding box
 //                    (2DGS surfel model, Sec. 3.1; low-pass filter, Sec. 3.2)
+//   orc_tile_reach   which tiles of a surfel's rect its cutoff region can reach (the list rule)
 //   orc_bin          per-tile lists ordered by (fp32 depth bits, id) using std::sort
 //   orc_render       front-to-back alpha blending of Eq. 1 per pixel, over the tile lists
 //   orc_render_brute the same blend over *all* surviving surfels (no tiling): pins the lists
@@ -326,9 +327,10 @@ struct PixOut {
 
 // One pixel's front-to-back blend over an ordered list of surfel indices.  'order[e]' gives
 // the surfel of list entry e; entries [start, end).
-// on_frag(n, alpha, T) is called for every contributing fragment with the transmittance in front of it.
+// on_frag(n, alpha, T, dalpha, dT) is called for every contributing fragment with the transmittance in
+// front of it and the relative error bounds of alpha and T under the FP32 error model.
 struct NoFrag {
-  void operator()(int64_t, double, double) const {}
+  void operator()(int64_t, double, double, double, double) const {}
 };
 
 template <class IdOf, class OnFrag = NoFrag>
@@ -362,7 +364,7 @@ void blend_pixel(IdOf id_of, int64_t start, int64_t end, const double* M, const 
     margin = std::min(margin, relmargin(T, 0.5) - dT);
     dT = dTn;
     mix((uint64_t)n * 4 + (e.is3d ? 1 : 0) + (e.clamped ? 2 : 0));
-    on_frag(n, e.alpha, T);
+    on_frag(n, e.alpha, T, e.clamped ? 0.0 : e.dalpha_rel, dT);
     const double w = e.alpha * T;
     for (int c = 0; c < 3; ++c) { C[c] += w * rgb[3 * n + c]; N[c] += w * nrm[3 * n + c]; }
     D += w * e.zf;
@@ -391,7 +393,7 @@ void store_pix(const PixOut& po, int64_t p, int64_t HW, double* out_rgb, double*
 template <class Range>
 void contribution_pass(Range range, const double* M, const double* rgb, const double* nrm, const double* opac,
                        const Cam& cam, double gamma, double fragile_thr, double* out_sum, int64_t* out_cnt,
-                       int32_t* out_fragile) {
+                       int32_t* out_fragile, double* out_err) {
 #pragma omp parallel for schedule(dynamic)
   for (int j = 0; j < cam.H; ++j) {
     for (int i = 0; i < cam.W; ++i) {
@@ -399,12 +401,19 @@ void contribution_pass(Range range, const double* M, const double* rgb, const do
       auto id_of = range(i, j, start, end);
       PixOut po;
       blend_pixel(id_of, start, end, M, rgb, nrm, opac, cam, i + 0.5, j + 0.5, po,
-                  [&](int64_t n, double alpha, double T) {
+                  [&](int64_t n, double alpha, double T, double da, double dT) {
                     const double c = std::pow(alpha, gamma) * std::pow(T, 1 - gamma);
 #pragma omp atomic
                     out_sum[n] += c;
 #pragma omp atomic
                     out_cnt[n] += 1;
+                    if (out_err) {
+                      // first-order error of c = alpha^g T^(1-g) from those of alpha and T, plus the FP32
+                      // evaluation of exp2(g log2 alpha + (1 - g) log2 T) (argument error ~ 16 ulp)
+                      const double e = c * (gamma * da + (1 - gamma) * dT + 16 * kU32);
+#pragma omp atomic
+                      out_err[n] += e;
+                    }
                   });
       if (po.margin < fragile_thr)
         for (int64_t k = start; k < start + po.n_eval; ++k) {
@@ -413,6 +422,49 @@ void contribution_pass(Range range, const double* M, const double* rgb, const do
         }
     }
   }
+}
+
+// Tile reach helpers (see orc_tile_reach).
+void cross(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// x in [xl, xh], y in [yl, yh], centre-relative
+bool tile_reached(const double* M, double K, double xl, double xh, double yl, double yh) {
+  // screen-filter branch: rho2d = 2 |x - c|^2
+  const double dx = xl > 0 ? xl : (xh < 0 ? xh : 0.0), dy = yl > 0 ? yl : (yh < 0 ? yh : 0.0);
+  if (2 * (dx * dx + dy * dy) <= K) return true;
+  double c1[3], c2[3], c3[3];
+  cross(M + 3, M + 6, c1);
+  cross(M + 6, M, c2);
+  cross(M, M + 3, c3);
+  const double cx = M[2] / M[8], cy = M[5] / M[8];
+  double pc[3];
+  for (int k = 0; k < 3; ++k) pc[k] = cx * c1[k] + cy * c2[k] + c3[k];
+  // q(x, y) = Q00 x^2 + 2 Q01 x y + Q11 y^2 + 2 B0 x + 2 B1 y + D
+  auto dot = [&](const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] - K * u[2] * v[2]; };
+  const double Q00 = dot(c1, c1), Q01 = dot(c1, c2), Q11 = dot(c2, c2);
+  const double B0 = dot(c1, pc), B1 = dot(c2, pc), D = dot(pc, pc);
+  const double det = Q00 * Q11 - Q01 * Q01;
+  if (!(Q00 > 0 && Q11 > 0 && det > 0)) return true;
+  const double xs = -(Q11 * B0 - Q01 * B1) / det, ys = -(Q00 * B1 - Q01 * B0) / det;
+  if (xs >= xl && xs <= xh && ys >= yl && ys <= yh) return true;
+  auto q = [&](double x, double y) { return Q00 * x * x + 2 * Q01 * x * y + Q11 * y * y + 2 * B0 * x + 2 * B1 * y + D; };
+  auto clamp = [](double v, double lo, double hi) { return std::min(std::max(v, lo), hi); };
+  double best = INFINITY;
+  for (double X : {xl, xh}) best = std::min(best, q(X, clamp(-(Q01 * X + B1) / Q11, yl, yh)));
+  for (double Y : {yl, yh}) best = std::min(best, q(clamp(-(Q01 * Y + B0) / Q00, xl, xh), Y));
+  return best <= 0;
+}
+
+bool tile_reach_at(const double* M, double k2, int tx, int ty, double Kscale, double pad) {
+  const double K = (k2 * (1 + 2e-3) + 2e-3) * Kscale;
+  const double cx = M[2] / M[8], cy = M[5] / M[8];
+  const double xl = kTile * tx + 0.5 - pad - cx, xh = kTile * tx + kTile - 0.5 + pad - cx;
+  const double yl = kTile * ty + 0.5 - pad - cy, yh = kTile * ty + kTile - 0.5 + pad - cy;
+  return tile_reached(M, K, xl, xh, yl, yh);
 }
 
 }  // namespace
@@ -497,20 +549,63 @@ int orc_project(int64_t n, int deg, const double* mean, const double* log_scale,
 }
 
 // ------------------------------------------------------------------------------------------
-// Binning: for each tile, the surfels whose tile rect covers it, ordered by (float32 bits of the
-// centre depth, id).  offsets[tiles + 1]; ids[K].  Returns K (ids untouched if cap < K).
+// Tile reach (which tiles of a surfel's rect can hold a blended pixel; reading of the binning).
+// A tile lists the surfel when some point of its pixel-sample box [16 tx + 0.5, 16 tx + 15.5] x
+// [16 ty + 0.5, 16 ty + 15.5], padded by 1/64 px, has rho = min(rho3d, rho2d) <= K with the cutoff
+// enlarged to K = k2 (1 + 2e-3) + 2e-3.  (A pixel can only take the surfel where rho <= k2; the
+// enlargement keeps every such pixel whatever the rounding of an FP32 evaluation.)
+//   rho2d <= K  <=>  |x - c|^2 <= K / 2: the distance from the projected centre c to the box;
+//   rho3d <= K  <=>  q(x) = p0^2 + p1^2 - K p2^2 <= 0, with p = a x b of evaluate() linear in x:
+//                    p = x (m2 x m3) + y (m3 x m1) + m1 x m2.  When the quadratic part of q is positive
+//                    definite the set is an ellipse and q is convex: it meets the box iff its minimiser
+//                    lies in the box or q <= 0 at the minimum along one of the four edges.  Otherwise
+//                    (the cutoff ellipse on the surfel's plane reaches the camera plane) every tile of
+//                    the rect is kept.
+// keep[j] / fragile[j] for the rect tiles of the visible surfels in order (surfel, then tile rows);
+// fragile marks decisions that change between K (1 -+ 1e-5) with the pad -+ 1e-3 px.
 // ------------------------------------------------------------------------------------------
-int64_t orc_bin(int64_t n, int W, int H, const int32_t* tile_rect, const float* depth32, int64_t* offsets,
-                int32_t* ids, int64_t cap) {
+
+int64_t orc_tile_reach(int64_t n, const double* M, const double* k2, const int32_t* tile_rect, uint8_t* keep,
+                       uint8_t* fragile) {
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* r = tile_rect + 4 * i;
+    start[i + 1] = start[i] + (int64_t)std::max(0, r[2] - r[0]) * std::max(0, r[3] - r[1]);
+  }
+  if (!keep) return start[n];
+  const double pad = 1.0 / 64.0;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* r = tile_rect + 4 * i;
+    int64_t j = start[i];
+    for (int y = r[1]; y < r[3]; ++y)
+      for (int x = r[0]; x < r[2]; ++x, ++j) {
+        keep[j] = tile_reach_at(M + 9 * i, k2[i], x, y, 1.0, pad);
+        if (fragile)
+          fragile[j] = tile_reach_at(M + 9 * i, k2[i], x, y, 1 + 1e-5, pad + 1e-3) !=
+                       tile_reach_at(M + 9 * i, k2[i], x, y, 1 - 1e-5, pad - 1e-3);
+      }
+  }
+  return start[n];
+}
+
+// ------------------------------------------------------------------------------------------
+// Binning: for each tile, the surfels whose tile rect covers it (and, when keep is given, whose
+// rect-tile entry of orc_tile_reach is set), ordered by (float32 bits of the centre depth, id).
+// offsets[tiles + 1]; ids[K].  Returns K (ids untouched if cap < K).
+// ------------------------------------------------------------------------------------------
+int64_t orc_bin(int64_t n, int W, int H, const int32_t* tile_rect, const float* depth32, const uint8_t* keep,
+                int64_t* offsets, int32_t* ids, int64_t cap) {
   const int tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
   std::vector<std::vector<std::pair<uint64_t, int32_t>>> lists((size_t)tx * ty);
+  int64_t j = 0;
   for (int64_t i = 0; i < n; ++i) {
     const int32_t* r = tile_rect + 4 * i;
     uint32_t bits;
     std::memcpy(&bits, depth32 + i, 4);
     for (int y = r[1]; y < r[3]; ++y)
-      for (int x = r[0]; x < r[2]; ++x)
-        lists[(size_t)y * tx + x].push_back({((uint64_t)bits << 32) | (uint32_t)i, (int32_t)i});
+      for (int x = r[0]; x < r[2]; ++x, ++j)
+        if (!keep || keep[j]) lists[(size_t)y * tx + x].push_back({((uint64_t)bits << 32) | (uint32_t)i, (int32_t)i});
   }
   int64_t K = 0;
   offsets[0] = 0;
@@ -628,11 +723,13 @@ int orc_render_brute(int64_t n, const double* M, const double* rgb, const double
 // it, and |P_k|; C_{n,k} = sum / |P_k| (0 when P_k is empty).  fragile[n] counts the pixels at which
 // the surfel is evaluated and whose smallest decision margin is below fragile_thr (there an FP32
 // evaluation may decide differently, moving the surfel's count by at most 1 and its sum by at most one
-// term).  Accumulates into out_sum / out_cnt / out_fragile (caller zeroes).
+// term).  out_err (optional) receives a first-order bound of the error an FP32 evaluation makes in the
+// sum, from the FP32 error model of alpha and T.  Accumulates into out_sum / out_cnt / out_fragile /
+// out_err (caller zeroes).
 // ------------------------------------------------------------------------------------------
 int orc_contribution(int64_t n, const double* M, const double* rgb, const double* nrm, const double* opac,
                      const double* camv, const int64_t* offsets, const int32_t* ids, double gamma, double fragile_thr,
-                     double* out_sum, int64_t* out_cnt, int32_t* out_fragile) {
+                     double* out_sum, int64_t* out_cnt, int32_t* out_fragile, double* out_err) {
   (void)n;
   const Cam cam = load_cam(camv);
   const int tx = (cam.W + kTile - 1) / kTile;
@@ -643,7 +740,7 @@ int orc_contribution(int64_t n, const double* M, const double* rgb, const double
         end = offsets[t + 1];
         return [ids](int64_t k) { return (int64_t)ids[k]; };
       },
-      M, rgb, nrm, opac, cam, gamma, fragile_thr, out_sum, out_cnt, out_fragile);
+      M, rgb, nrm, opac, cam, gamma, fragile_thr, out_sum, out_cnt, out_fragile, out_err);
   return 0;
 }
 
@@ -666,7 +763,7 @@ int orc_contribution_brute(int64_t n, const double* M, const double* rgb, const 
         end = (int64_t)ord->size();
         return [ord](int64_t k) { return (*ord)[k].second; };
       },
-      M, rgb, nrm, opac, cam, gamma, -1.0, out_sum, out_cnt, fragile.data());
+      M, rgb, nrm, opac, cam, gamma, -1.0, out_sum, out_cnt, fragile.data(), nullptr);
   return 0;
 }
 

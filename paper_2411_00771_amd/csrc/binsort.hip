@@ -5,11 +5,13 @@
 //   surfel scan   one fused three-kernel pass over every (view, surfel): the exclusive prefix sum of
 //                 its tile count (from its rect) and the compaction of the visible ones into per-view
 //                 lists, plus the capacity check
-//   k_stage       groups of lanes per visible surfel: for each covered tile, a returning atomic on the
-//                 tile's counter gives the entry's rank within the tile; (tile, rank, depth bits << 32 |
-//                 id) goes to the surfel's own slice
+//   k_stage       groups of lanes per visible surfel: for each tile of its rect that the surfel's
+//                 alpha >= 1/255 region reaches (reach_cell over the tile's pixel samples), a returning
+//                 atomic on the tile's counter gives the entry's rank within the tile; (tile, rank,
+//                 depth bits << 32 | id) goes to the surfel's own slice, a sentinel tile to the slots of
+//                 the rect tiles it cannot reach
 //   k_tile_scan   one workgroup: exclusive prefix sum of the V * tiles counters -> ranges
-//   k_place       one thread per intersection: keys[ranges[tile] + rank] = key (no atomics)
+//   k_place       one thread per staged slot: keys[ranges[tile] + rank] = key (no atomics)
 //   k_sort_small  one workgroup per tile: LDS bitonic sort of lists up to kSmall entries
 //   k_sort_big    lists up to kBig entries in 128 KB of LDS; longer lists are sorted in kBig chunks
 //                 and merged in global memory by rank (binary search)
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
 // Groups of 32 lanes take one visible surfel of view blockIdx.y each and spread its tiles over the
 // group, so a surfel that covers hundreds of tiles does not hold up a wave.
 constexpr int kGroup = 32;
+constexpr uint32_t kNoTile = 0xffffffffu;  // staged slot of a rect tile the surfel cannot reach
 __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect, const float* __restrict__ rec,
                                                int64_t n, int tiles_x, int tiles_per_view,
                                                const uint32_t* __restrict__ visible,
@@ -174,23 +177,32 @@ __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect
     uint32_t tx0, ty0, tx1, ty1;
     tile_rect(rect + 4 * vi, tx0, ty0, tx1, ty1);
     const uint32_t w = tx1 - tx0, total = w * (ty1 - ty0);
-    const uint64_t key = ((uint64_t)__float_as_uint(rec[vi * kRec + R_ZC]) << 32) | i;
+    const float4* rp = (const float4*)(rec + vi * kRec);
+    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r4 = rp[4];
+    const uint64_t key = ((uint64_t)__float_as_uint(r2.w) << 32) | i;
+    Reach q;
+    reach_setup(r1.x * kInvSqrt2, r1.y * kInvSqrt2, r1.z * kInvSqrt2, r1.w * kInvSqrt2, r2.x, r2.y, r2.z, r4.w, q);
     const uint32_t o = soff[vi];
     // four independent returning atomics in flight per lane before their results are used
     for (uint32_t k0 = g; k0 < total; k0 += 4 * kGroup) {
       uint32_t t[4], r[4];
+      bool keep[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t k = k0 + (uint32_t)j * kGroup;
-        t[j] = tbase + (ty0 + k / w) * tiles_x + tx0 + k % w;
-        r[j] = k < total ? atomicAdd(cnt + t[j], 1u) : 0u;
+        const uint32_t tx = tx0 + k % w, ty = ty0 + k / w;
+        t[j] = tbase + ty * tiles_x + tx;
+        // the tile-relative centre exactly as the renderer stages it
+        const float fox = (float)(tx * kTile), foy = (float)(ty * kTile);
+        keep[j] = k < total && reach_cell(q, (r0.x - fox) + r0.z, (r0.y - foy) + r0.w, 0, 0, kTile);
+        r[j] = keep[j] ? atomicAdd(cnt + t[j], 1u) : 0u;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t k = k0 + (uint32_t)j * kGroup;
         if (k < total) {
-          st_pos[o + k] = make_uint2(t[j], r[j]);
-          st_key[o + k] = key;
+          st_pos[o + k] = make_uint2(keep[j] ? t[j] : kNoTile, r[j]);
+          if (keep[j]) st_key[o + k] = key;
         }
       }
     }
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ soff
   const uint32_t K = *soff_total;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
     const uint2 tp = st_pos[e];
-    keys[ranges[tp.x] + tp.y] = st_key[e];
+    if (tp.x != kNoTile) keys[ranges[tp.x] + tp.y] = st_key[e];
   }
 }
 

@@ -111,6 +111,73 @@ __device__ __forceinline__ float reduce16_scatter(float (&v)[16]) {
   return t;
 }
 
+// Where a surfel can reach alpha >= 1/255 (Sec. 3.1 cutoff).  rho is the smaller of the ray-splat
+// distance |A x|^2 / w(x)^2 and the screen-filter distance |x|^2, both halved (x relative to the
+// projected centre; A = the record's a_ij / sqrt 2, w(x) = w0 + w1 x + w2 y as the renderer stages
+// them, so this is the function its evaluation rounds), and the cutoff is rho <= ln(255 o) = k2 / 2.
+// {|A x|^2 <= c w(x)^2} is the conic g(x) = x'Gx + 2 b'x + d <= 0; when G is positive definite it is an
+// ellipse, met by a box iff its centre lies in the box or g <= 0 somewhere on one of the four edges
+// (g is convex, so each edge's minimum is at the clamped stationary point).  FP64, with the cutoff
+// enlarged to c = 0.5 k2 (1 + 2e-3) + 1e-3 and every box padded by kReachPad: far beyond the FP32
+// error of the evaluation and of the reciprocals used here, so a box is reported unreachable only
+// where no pixel sample in it can take the surfel.  A conic that is not an ellipse reaches every box.
+constexpr float kInvSqrt2 = 0.70710678118654752440f;
+constexpr double kReachPad = 1.0 / 64.0;
+
+struct Reach {
+  double G00, G01, G11, b0, b1, d, c, i00, i11, xs, ys;
+  bool ellipse;
+};
+
+__device__ __forceinline__ void reach_setup(float a11, float a12, float a21, float a22, float w0f, float w1f, float w2f,
+                                            float k2, Reach& q) {
+  q.c = 0.5 * (double)k2 * (1.0 + 2e-3) + 1e-3;
+  const double A11 = a11, A12 = a12, A21 = a21, A22 = a22, w0 = w0f, w1 = w1f, w2 = w2f, c = q.c;
+  q.G00 = A11 * A11 + A21 * A21 - c * w1 * w1;
+  q.G01 = A11 * A12 + A21 * A22 - c * w1 * w2;
+  q.G11 = A12 * A12 + A22 * A22 - c * w2 * w2;
+  const double det = q.G00 * q.G11 - q.G01 * q.G01;
+  q.ellipse = q.G00 > 0.0 && q.G11 > 0.0 && det > 0.0 && det < 1e300;
+  q.b0 = -c * w0 * w1;
+  q.b1 = -c * w0 * w2;
+  q.d = -c * w0 * w0;
+  // single-precision reciprocals are enough: they only place the points at which g is evaluated
+  const float r00 = __builtin_amdgcn_rcpf((float)q.G00), r11 = __builtin_amdgcn_rcpf((float)q.G11);
+  const float rdet = __builtin_amdgcn_rcpf((float)det);
+  // (a reciprocal that overflows or underflows in single precision leaves the conic unused)
+  const bool fin = isfinite(r00) && isfinite(r11) && isfinite(rdet) && r00 > 0.f && r11 > 0.f && rdet > 0.f;
+  q.ellipse = q.ellipse && fin;
+  q.i00 = q.ellipse ? (double)r00 : 0.0;
+  q.i11 = q.ellipse ? (double)r11 : 0.0;
+  const double idet = q.ellipse ? (double)rdet : 0.0;
+  q.xs = -(q.G11 * q.b0 - q.G01 * q.b1) * idet;
+  q.ys = -(q.G00 * q.b1 - q.G01 * q.b0) * idet;
+}
+
+// Does the box [xl, xh] x [yl, yh] (centre-relative, already padded) hold a point with rho <= c?
+__device__ __forceinline__ bool reach_box(const Reach& q, double xl, double xh, double yl, double yh) {
+  // screen-filter disc |x|^2 <= c
+  const double dx = xl > 0.0 ? xl : (xh < 0.0 ? xh : 0.0), dy = yl > 0.0 ? yl : (yh < 0.0 ? yh : 0.0);
+  if (dx * dx + dy * dy <= q.c) return true;
+  if (!q.ellipse || (q.xs >= xl && q.xs <= xh && q.ys >= yl && q.ys <= yh)) return true;
+  auto g = [&](double x, double y) {
+    return fma(q.G00 * x, x, fma(2.0 * q.G01 * x, y, fma(q.G11 * y, y, fma(2.0 * q.b0, x, fma(2.0 * q.b1, y, q.d)))));
+  };
+  const double yA = fmin(fmax(-(q.G01 * xl + q.b1) * q.i11, yl), yh);
+  const double yB = fmin(fmax(-(q.G01 * xh + q.b1) * q.i11, yl), yh);
+  const double xA = fmin(fmax(-(q.G01 * yl + q.b0) * q.i00, xl), xh);
+  const double xB = fmin(fmax(-(q.G01 * yh + q.b0) * q.i00, xl), xh);
+  return fmin(fmin(g(xl, yA), g(xh, yB)), fmin(g(xA, yl), g(xB, yh))) <= 0.0;
+}
+
+// Box of the pixel samples [x0 + 0.5, x0 + span - 0.5] x [y0 + ...] of a tile-relative cell, relative to
+// the tile-relative centre (cxt, cyt), padded.
+__device__ __forceinline__ bool reach_cell(const Reach& q, float cxt, float cyt, int x0, int y0, int span) {
+  const double xl = (double)x0 + 0.5 - (double)cxt - kReachPad, xh = xl + (double)(span - 1) + 2.0 * kReachPad;
+  const double yl = (double)y0 + 0.5 - (double)cyt - kReachPad, yh = yl + (double)(span - 1) + 2.0 * kReachPad;
+  return reach_box(q, xl, xh, yl, yh);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)

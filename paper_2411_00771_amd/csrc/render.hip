@@ -22,7 +22,6 @@
 
 namespace cgv2 {
 
-constexpr float kInvSqrt2 = 0.70710678118654752440f;
 constexpr float kLog2e = 1.44269504088896340736f;
 
 struct RenderArgs {
@@ -65,53 +64,14 @@ struct Stage {
   uint32_t qm[64];
 };
 
-// Quadrants (bits of 'm') in which some pixel sample can reach alpha >= 1/255.  rho is the smaller of
-// the ray-splat distance |A x|^2 / w(x)^2 and the screen-filter distance |x|^2 (x relative to the
-// projected centre; A, w as staged, so this is the function the evaluation rounds), and the cutoff is
-// rho <= c = ln(255 o) = k2 / 2.  {|A x|^2 <= c w(x)^2} is the conic g(x) = x'Gx + 2 b'x + d <= 0; when
-// G is positive definite it is an ellipse, met by a box iff its centre lies inside the box or the
-// minimum of g over one of the four edges is <= 0.  FP64 throughout, with the cutoff enlarged by
-// 2e-3 relative + 1e-3 and the box by 1/64 px, far beyond the FP32 error of the evaluation, so a
-// quadrant is dropped only where no pixel can take the surfel.  A conic that is not an ellipse keeps
-// the rect's quadrants.
-__device__ __forceinline__ uint32_t reach_quadrants(uint32_t m, float cxt, float cyt, float a11, float a12, float a21,
-                                                    float a22, float w0f, float w1f, float w2f, float k2) {
-  const double c = 0.5 * (double)k2 * (1.0 + 2e-3) + 1e-3;
-  const double A11 = a11, A12 = a12, A21 = a21, A22 = a22, w0 = w0f, w1 = w1f, w2 = w2f;
-  const double G00 = A11 * A11 + A21 * A21 - c * w1 * w1;
-  const double G01 = A11 * A12 + A21 * A22 - c * w1 * w2;
-  const double G11 = A12 * A12 + A22 * A22 - c * w2 * w2;
-  const double det = G00 * G11 - G01 * G01;
-  const bool ellipse = G00 > 0.0 && G11 > 0.0 && det > 0.0;
-  const double b0 = -c * w0 * w1, b1 = -c * w0 * w2, d = -c * w0 * w0;
-  const double i00 = ellipse ? 1.0 / G00 : 0.0, i11 = ellipse ? 1.0 / G11 : 0.0, idet = ellipse ? 1.0 / det : 0.0;
-  const double xs = -(G11 * b0 - G01 * b1) * idet, ys = -(G00 * b1 - G01 * b0) * idet;
-  auto g = [&](double x, double y) {
-    return fma(G00 * x, x, fma(2.0 * G01 * x, y, fma(G11 * y, y, fma(2.0 * b0, x, fma(2.0 * b1, y, d)))));
-  };
-  constexpr double kPad = 1.0 / 64.0;
+// Quadrants (bits of 'm') in which some pixel sample can reach alpha >= 1/255 (reach_setup / reach_cell).
+__device__ __forceinline__ uint32_t reach_quadrants(uint32_t m, const float4& q0, const float4& q1, float w2, float k2) {
+  Reach r;
+  reach_setup(q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, w2, k2, r);
   uint32_t out = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (!((m >> k) & 1u)) continue;
-    const double xl = (double)(8 * (k & 1)) + 0.5 - (double)cxt - kPad, xh = xl + 7.0 + 2.0 * kPad;
-    const double yl = (double)(8 * (k >> 1)) + 0.5 - (double)cyt - kPad, yh = yl + 7.0 + 2.0 * kPad;
-    // screen-filter disc |x|^2 <= c
-    const double dx = xl > 0.0 ? xl : (xh < 0.0 ? xh : 0.0), dy = yl > 0.0 ? yl : (yh < 0.0 ? yh : 0.0);
-    bool hit = dx * dx + dy * dy <= c;
-    if (!hit) {
-      if (!ellipse || (xs >= xl && xs <= xh && ys >= yl && ys <= yh)) {
-        hit = true;
-      } else {
-        const double yA = fmin(fmax(-(G01 * xl + b1) * i11, yl), yh);
-        const double yB = fmin(fmax(-(G01 * xh + b1) * i11, yl), yh);
-        const double xA = fmin(fmax(-(G01 * yl + b0) * i00, xl), xh);
-        const double xB = fmin(fmax(-(G01 * yh + b0) * i00, xl), xh);
-        hit = fmin(fmin(g(xl, yA), g(xh, yB)), fmin(g(xA, yl), g(xB, yh))) <= 0.0;
-      }
-    }
-    out |= hit ? 1u << k : 0u;
-  }
+  for (int k = 0; k < 4; ++k)
+    if (((m >> k) & 1u) && reach_cell(r, q0.x, q0.y, 8 * (k & 1), 8 * (k >> 1), 8)) out |= 1u << k;
   return out;
 }
 
@@ -142,7 +102,7 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
     if (i0 <= x0 + 7 && i1 >= x0 && j0 <= y0 + 7 && j1 >= y0) m |= 1u << k;
   }
   if (qmask) m &= qmask[idx];
-  else if (m) m = reach_quadrants(m, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r2.z, r4.w);
+  else if (m) m = reach_quadrants(m, q0, q1, r2.z, r4.w);
   s.qm[lane] = valid ? m : 0u;
 }
 

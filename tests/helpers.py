@@ -76,3 +76,42 @@ def grad_close(name, g, ref, rel=GRAD_REL):
     # elementwise: allow a handful of outliers from fp32 cancellation, never more than 0.1 %
     assert bad.mean() <= 1e-3, f"{name}: {bad.sum()} elements outside the elementwise bound"
     return err
+
+
+def compare_lists(ranges, ids, po, cam, P=None, v=0, max_excluded=None):
+    """GPU tile lists against the oracle's (its own projection `po`, the reach rule of
+    ``oracle.bin_view``), entry for entry and in order.  Left out on both sides: the surfels whose
+    projection decisions differ (visibility, tile rect or depth key; only when the GPU projection `P` is
+    given) and the (tile, surfel) pairs whose reach decision the oracle marks fragile.  Returns the
+    counts left out."""
+    import oracle
+    off, oids, info = oracle.bin_view(po, cam)
+    n = po["tile_rect"].shape[0]
+    T = len(off) - 1
+    assert len(ranges) == T + 1
+    excl = np.zeros(n, bool)
+    if P is not None:
+        vis_g, vis_o = (P["flags"][v] & 1) > 0, (po["flags"] & 1) > 0
+        excl |= vis_g != vis_o
+        both = vis_g & vis_o
+        excl |= both & (P["rect"][v] != po["tile_rect"]).any(1)
+        kg = P["rec"][v, :, 11].astype(np.float32).view(np.uint32)
+        excl |= both & (kg != po["depth32"].view(np.uint32))
+    fr = np.sort(np.asarray(info["fragile"], np.int64))
+
+    def left_out(rng, lst):
+        tile = np.repeat(np.arange(T, dtype=np.int64), np.diff(rng))
+        key = tile * n + lst
+        pos = np.searchsorted(fr, key)
+        hit = (pos < fr.size) & (fr[np.minimum(pos, max(fr.size - 1, 0))] == key) if fr.size else np.zeros(key.size, bool)
+        return excl[lst] | hit, tile
+
+    mg, tg = left_out(np.asarray(ranges, np.int64), np.asarray(ids, np.int64))
+    mo, to = left_out(off, np.asarray(oids, np.int64))
+    assert np.array_equal(np.bincount(tg[~mg], minlength=T), np.bincount(to[~mo], minlength=T)), "per-tile counts"
+    assert np.array_equal(np.asarray(ids)[~mg], np.asarray(oids)[~mo]), "list order"
+    out = dict(surfels=int(excl.sum()), fragile_pairs=int(fr.size), entries_g=int(mg.sum()), entries_o=int(mo.sum()),
+               rect_total=info["rect_total"], listed=int(len(oids)))
+    if max_excluded is not None:
+        assert out["surfels"] + out["fragile_pairs"] <= max_excluded, out
+    return out

@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size: 1 M surfels on the aerial city, 1600x1066, launched exactly as
-bench.py launches it (one view per call).  Lists are compared in full (bit-exact); images on sampled
+bench.py launches it (one view per call).  Lists are compared in full (bit-exact but for rounding ties
+of the projection and fragile reach decisions, both counted and bounded); images on sampled
 tiles the oracle renders one by one; gradients with the upstream restricted to the sampled tiles, so
 the oracle's reverse pass covers exactly what the GPU's does; loss and densify in full."""
 import numpy as np
@@ -7,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2411_00771_amd import scenes
-from tests.helpers import FRAGILE, IMG_TOL, fetch_bins, fetch_proj, grad_close
+from tests.helpers import FRAGILE, IMG_TOL, compare_lists, fetch_bins, fetch_proj, grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +47,12 @@ def test_aerial_bins_bit_exact_and_images_on_sampled_tiles(aerial, view):
     eng, cam = v["eng"], v["cam"]
     P = fetch_proj(eng)
     ranges, ids = fetch_bins(eng)
-    o_off, o_ids = oracle.bin_tiles(P["rect"][0], P["rec"][0, :, 11].astype(np.float32), cam.width, cam.height)
-    assert np.array_equal(ranges, o_off) and np.array_equal(ids, o_ids)
     po = oracle.project(aerial["sc"], cam)
+    # every list entry for entry, except surfels whose projection decisions sit on a rounding tie and
+    # fragile reach decisions
+    r = compare_lists(ranges, ids, po, cam, P=P)
+    print(f"[aerial] view {view}: lists {r}", flush=True)
+    assert r["surfels"] <= 16 and r["fragile_pairs"] <= 5e-4 * r["listed"]
     vis = (po["flags"] & 1) > 0
     assert np.mean(vis != ((P["flags"][0] & 1) > 0)) < 1e-5
     both = vis & ((P["flags"][0] & 1) > 0)
@@ -59,7 +63,7 @@ def test_aerial_bins_bit_exact_and_images_on_sampled_tiles(aerial, view):
     M = po["M"][both]
     cx = P["rec"][0, both, 0].astype(np.float64) + P["rec"][0, both, 2]
     assert np.abs(cx - M[:, 2] / M[:, 8]).max() < 2e-5
-    off, oids = oracle.bin_tiles(po["tile_rect"], po["depth32"], cam.width, cam.height)
+    off, oids, _ = oracle.bin_view(po, cam)
     tiles = _sample_tiles(eng, ranges)
     ref, ne, nc = oracle.render_tiles(po, cam, off, oids, tiles)
     tx = eng.tiles_x
@@ -114,7 +118,7 @@ def test_aerial_backward_on_sampled_tiles_and_densify(aerial, cuda):
         oy, ox = (t // tx) * 16, (t % tx) * 16
         mask_px[oy:oy + 16, ox:ox + 16] = True
     po = oracle.project(sc, cam)
-    off, oids = oracle.bin_tiles(po["tile_rect"], po["depth32"], W, H)
+    off, oids, _ = oracle.bin_view(po, cam)
     ref_tiles, _, _ = oracle.render_tiles(po, cam, off, oids, tiles)
     # exclude pixels whose decisions are fragile
     for s, t in enumerate(tiles):

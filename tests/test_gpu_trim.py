@@ -1,8 +1,10 @@
 """Contribution-based trimming (Sec. 3.3, Eq. 3/4 and the percentile bound) against the oracle.
 
 Per-surfel contributions: where the oracle finds no fragile pixel among those a surfel is evaluated at
-(a pixel whose decisions fall inside the FP32 error bound), pixel counts |P| exactly and C to a relative
-1e-4 (FP32 terms alpha^gamma T^(1-gamma), summed in arbitrary atomic order); with fp such pixels, the count
+(a pixel whose decisions fall inside the FP32 error bound), pixel counts |P| exactly and C within the
+oracle's first-order FP32 error bound of the terms alpha^gamma T^(1-gamma) plus 1e-5 relative and the
+rounding bound of their FP32 sum (one wave reduction and one atomic add per tile or quadrant block, in
+arbitrary order); with fp such pixels, the count
 within fp and the sum within fp terms (each term is at most 1).  The trimming bound is
 checked bit for bit against its definition applied to the GPU's own contributions, and against the
 oracle's average over views."""
@@ -15,9 +17,19 @@ from tests.helpers import FRAGILE, gpu_forward
 
 pytestmark = pytest.mark.gpu
 
-# each term alpha^gamma T^(1-gamma) carries the FP32 error of alpha (up to ~5e-5 relative for the
-# ill-conditioned surfels of the error model behind the fragility margins) and of the accumulated T
-C_REL = 1e-4
+# each term alpha^gamma T^(1-gamma) carries the FP32 error of alpha and of the accumulated T: the oracle
+# bounds it per surfel (ref["err"], the error model behind the fragility margins); 1e-5 relative on top
+C_REL = 1e-5
+U32 = 2.0 ** -24
+
+
+def _sum_tol(po, ref):
+    """Absolute bound of the GPU's FP32 sum of a surfel's terms: the terms' own error (ref["err"]) plus
+    the rounding of their summation (one wave reduction per tile or quadrant block, one atomic add of
+    each partial: at most min(|P|, 4 x rect tiles) of them) and C_REL."""
+    r = po["tile_rect"].astype(np.int64)
+    tiles = np.maximum(r[:, 2] - r[:, 0], 0) * np.maximum(r[:, 3] - r[:, 1], 0)
+    return ref["err"] + (C_REL + U32 * (np.minimum(ref["cnt"], 4 * tiles) + 8)) * ref["sum"]
 
 
 def _gpu_contrib(eng, cs, gamma):
@@ -41,11 +53,21 @@ def _check_view(sc, cam, c_gpu, px_gpu, flags_gpu, gamma, min_exact):
     # surfels evaluated at fragile pixels: count within fp, sum within fp terms
     fr = both & (fp > 0)
     assert np.all(np.abs(px_gpu[fr] - ref["cnt"][fr]) <= fp[fr])
+    tol = _sum_tol(po, ref)
     s_gpu = c_gpu[fr] * px_gpu[fr]
-    assert np.all(np.abs(s_gpu - ref["sum"][fr]) <= fp[fr] + C_REL * ref["sum"][fr])
+    assert np.all(np.abs(s_gpu - ref["sum"][fr]) <= fp[fr] + tol[fr])
     assert np.array_equal(px_gpu[ok], ref["cnt"][ok])
     err = np.abs(c_gpu[ok] - ref["C"][ok])
-    assert np.all(err <= C_REL * np.maximum(ref["C"][ok], 1e-6)), float((err / np.maximum(ref["C"][ok], 1e-6)).max())
+    # C = sum / |P|; the GPU's division and float32 result add two roundings
+    bound = tol[ok] / np.maximum(ref["cnt"][ok], 1) + 2 * U32 * ref["C"][ok] + 1e-12
+    bad = err > bound
+    if bad.any():
+        k = np.flatnonzero(ok)[bad]
+        print("[trim] outside the bound:", [(int(i), float(ref["C"][i]), float(c_gpu[i]), int(ref["cnt"][i]),
+                                             float(ref["err"][i])) for i in k[:8]], flush=True)
+    assert not bad.any(), float((err / bound).max())
+    print(f"[trim] C: {int(ok.sum())} surfels, worst error / bound {float((err / bound).max()):.3f}, "
+          f"median bound / C {float(np.median(bound[ref['C'][ok] > 0] / ref['C'][ok][ref['C'][ok] > 0])):.2e}", flush=True)
     # surfels the oracle never blends have C = 0 on both sides
     unseen = ok & (ref["cnt"] == 0)
     assert np.all(c_gpu[unseen] == 0)

@@ -22,6 +22,10 @@ P16 visibility frequency (Sec. 4 crop volume): the sphere-image box in closed fo
     against dense silhouette sampling off the axis; hand-placed visible / hidden points (behind the
     camera, between two pixel samples, off the image edge); counts as sums over views; the crop
     threshold, height range and ground coordinates under two transforms
+P18 the list rule (tile reach): a facing isotropic surfel keeps exactly the tiles within its cutoff
+    radius (closed form); on scenes of elongated, tilted surfels no tile with a pixel sample inside the
+    cutoff region is dropped (brute force over every sample), while most rect tiles outside it are;
+    images from the reach lists equal those from the plain rect lists and the brute-force render
 P17 serving storage: float16 rounding at known values, the importance partition, the nearest codeword
     against explicit loops and by construction (ties to the smaller index), the Lloyd update by hand
     (an empty codeword kept), the non-increasing k-means error, and decode(pack) within float16 rounding
@@ -147,14 +151,16 @@ def test_p4_invariants_tiny():
 
 def _brute_equal(sc, cam):
     proj = oracle.project(sc, cam)
-    off, ids = oracle.bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height)
-    tl = oracle.render(proj, cam, off, ids)
     br = oracle.render_brute(proj, cam)
-    for k in ("rgb", "depth", "depth_med", "normal", "alpha", "T"):
-        assert np.array_equal(tl[k], br[k]), k
-    ids_ext = np.append(ids, -1)
-    med_t = np.where(tl["med"] >= 0, ids_ext[np.where(tl["med"] >= 0, tl["med"], len(ids))], -1)
-    assert np.array_equal(med_t, br["med_id"])
+    rect = oracle.bin_tiles(proj["tile_rect"], proj["depth32"], cam.width, cam.height)
+    reach = oracle.bin_view(proj, cam)[:2]
+    for off, ids in (rect, reach):  # the plain rect lists and the lists of the reach rule
+        tl = oracle.render(proj, cam, off, ids)
+        for k in ("rgb", "depth", "depth_med", "normal", "alpha", "T"):
+            assert np.array_equal(tl[k], br[k]), k
+        ids_ext = np.append(ids, -1)
+        med_t = np.where(tl["med"] >= 0, ids_ext[np.where(tl["med"] >= 0, tl["med"], len(ids))], -1)
+        assert np.array_equal(med_t, br["med_id"])
 
 
 def test_p5_tiled_equals_brute_force_tiny():
@@ -680,3 +686,76 @@ def test_p17_decode_of_pack_within_half_rounding():
     # a quantized surfel decodes to its float16 codeword
     cw = C[codes[0]].astype(np.float32).astype(np.float16).astype(np.float32).reshape(9, 3)
     assert np.array_equal(d["sh"][:, :, nf], cw)
+
+
+# ---- P18 the list rule ------------------------------------------------------------------------------
+
+def _pixel_rho(M, x, y):
+    """rho = min(rho3d, rho2d) of surfels M [m][9] at pixel samples x, y [m][k] (written out from Eq. 1's
+    ray-splat intersection: p = (x m3 - m1) x (y m3 - m2), u = p0 / p2, v = p1 / p2)."""
+    m1, m2, m3 = M[:, None, 0:3], M[:, None, 3:6], M[:, None, 6:9]
+    a = x[..., None] * m3 - m1
+    b = y[..., None] * m3 - m2
+    p = np.cross(a, b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rho3 = np.where(p[..., 2] != 0, (p[..., 0] ** 2 + p[..., 1] ** 2) / p[..., 2] ** 2, np.inf)
+    cx, cy = M[:, 2] / M[:, 8], M[:, 5] / M[:, 8]
+    rho2 = 2 * ((x - cx[:, None]) ** 2 + (y - cy[:, None]) ** 2)
+    return np.minimum(rho3, rho2)
+
+
+def test_p18_facing_surfel_keeps_tiles_within_its_radius():
+    cam = scenes.tiny_camera(256, 256)
+    for scale, logit in ((0.3, 1.3), (0.12, -1.0), (0.004, 2.0)):
+        P = one_surfel_scene([(0.05, -0.03, 0.0)], scale, logit)
+        proj = oracle.project(P, cam)
+        keep, fragile = oracle.tile_reach(proj)
+        sid, tile = oracle.rect_tiles(proj["tile_rect"], cam.width)
+        o = 1 / (1 + math.exp(-logit))
+        K = 2 * math.log(255 * o) * (1 + 2e-3) + 2e-3
+        # camera at distance 3 on the axis: plane units = screen offsets * 3 / f
+        R = max(math.sqrt(K) * scale * f32(cam.fx) / 3.0, math.sqrt(K / 2))
+        M = proj["M"][0]
+        cx, cy = M[2] / M[8], M[5] / M[8]
+        tx = (cam.width + 15) // 16
+        x0, y0 = 16.0 * (tile % tx), 16.0 * (tile // tx)
+        pad = 1 / 64
+        dx = np.maximum(np.maximum(x0 + 0.5 - pad - cx, cx - (x0 + 15.5 + pad)), 0)
+        dy = np.maximum(np.maximum(y0 + 0.5 - pad - cy, cy - (y0 + 15.5 + pad)), 0)
+        expect = dx * dx + dy * dy <= R * R
+        assert not fragile.any() or fragile.sum() <= 2
+        assert np.array_equal(keep[~fragile], expect[~fragile]), scale
+        if scale == 0.3:
+            assert (~keep).sum() >= 4  # the rect's corner tiles lie outside the circle
+
+
+def _elongated_scene(seed, n):
+    rng = np.random.default_rng(seed)
+    sc = scenes.tiny_scene(seed, n)
+    su = rng.uniform(np.log(0.02), np.log(0.3), n)
+    ratio = np.log(rng.uniform(5, 50, n))
+    sc.log_scale[0] = (su + ratio / 2).astype(np.float32)
+    sc.log_scale[1] = (su - ratio / 2).astype(np.float32)
+    sc.mean[:2] *= 1.4
+    return sc
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_p18_no_reachable_tile_dropped_brute_force(seed):
+    sc = _elongated_scene(seed, 300)
+    cam = scenes.tiny_camera(160, 112)
+    proj = oracle.project(sc, cam)
+    keep, fragile = oracle.tile_reach(proj)
+    sid, tile = oracle.rect_tiles(proj["tile_rect"], cam.width)
+    tx = (cam.width + 15) // 16
+    lx, ly = np.meshgrid(np.arange(16) + 0.5, np.arange(16) + 0.5)
+    x = (16 * (tile % tx))[:, None] + lx.reshape(-1)[None, :]
+    y = (16 * (tile // tx))[:, None] + ly.reshape(-1)[None, :]
+    rho = _pixel_rho(proj["M"][sid], x, y)
+    inside = (rho <= proj["k2"][sid][:, None]).any(1)
+    assert inside.sum() > 200
+    assert not np.any(inside & ~keep), "a tile with a pixel sample inside the cutoff region was dropped"
+    # tight: what is kept but holds no sample inside the region is a small share of the rect's dropouts
+    assert (~keep).sum() > 0.3 * (~inside).sum()
+    assert fragile.sum() <= max(2, int(1e-3 * keep.size))
+    _brute_equal(sc, cam)
