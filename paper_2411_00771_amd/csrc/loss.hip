@@ -3,172 +3,356 @@
 // gradient (Sec. 3.2, Eq. 2).
 //
 // SSIM (Wang et al. 2004): 11x11 separable Gaussian window (sigma 1.5), zero padding,
-// C1 = 0.01^2, C2 = 0.03^2.  The forward kernel computes the five local moments of each 16x16
-// output tile from a 26x26 LDS tile (two separable passes), the SSIM map and its three partial
-// derivatives (w.r.t. the local mean, E[x^2] and E[xy]) and deterministic per-block sums.  The
-// backward kernel correlates the three partial maps with the same window and combines them with
-// the L1 sign into dL/dI and d(lambda (1 - SSIM))/dI.
+// C1 = 0.01^2, C2 = 0.03^2.  Both kernels run one wave per strip of 64 columns x kStripH rows of one
+// image plane and walk down the strip: each input row (the 64 columns and a 5-column halo on either
+// side) goes through LDS once, its 11-tap horizontal sums enter a ring of the last 11 rows held in
+// registers, and each new row completes the vertical sums of one output row -- the only recomputation
+// is the 10-row halo at the strip's top.  The forward kernel computes the five local moments, the SSIM
+// map and its three partial derivatives (w.r.t. the local mean, E[x^2] and E[xy]) and deterministic
+// per-wave sums; the backward kernel correlates the three partial maps with the same window and
+// combines them with the L1 sign into dL/dI and d(lambda (1 - SSIM))/dI.
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
 namespace cgv2 {
 
 constexpr int kR = 5;
-constexpr int kSide = kTile + 2 * kR;  // 26
+constexpr int kTaps = 2 * kR + 1;       // 11
+constexpr int kStripW = 64;             // output columns per wave (one per lane)
+constexpr int kAhead = 2;               // rows loaded ahead of the one in use (queue slot = row % 2)
+constexpr int kLoops = 2;               // row loop iterations of 22 rows after the first 11
+constexpr int kInRows = kTaps + 2 * kTaps * kLoops;  // 55 input rows per strip
+constexpr int kStripH = kInRows - 2 * kR;            // 45 output rows per wave
+constexpr int kRowW = kStripW + 2 * kR;
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 
-struct Win { float g[11]; };
+struct Win { float g[kTaps]; };
 
-// Block -> (tile x, tile y, plane).  Hardware sends block b to XCD b % 8; XCD x takes the column band
-// [x * band, (x + 1) * band) of every plane, row by row, so the halos that neighbouring tiles share
-// (left/right and above/below) are read through one L2.  Blocks past the right edge do nothing.
-struct LossGrid {
-  int tx, ty, band;
+// Block -> (strip column, strip row, plane vc = v * 3 + channel).
+struct StripGrid {
+  int nx, ny;
 };
 
-__device__ __forceinline__ bool loss_tile(const LossGrid& lg, int& bx, int& by, int& vc) {
-  const uint32_t b = blockIdx.x;
-  const uint32_t x = b % 8u, k = b / 8u;
-  const uint32_t per_plane = (uint32_t)(lg.band * lg.ty);
-  vc = (int)(k / per_plane);
-  const uint32_t r = k % per_plane;
-  by = (int)(r / (uint32_t)lg.band);
-  bx = (int)(x * (uint32_t)lg.band + r % (uint32_t)lg.band);
-  return bx < lg.tx;
+__device__ __forceinline__ void strip_of_block(const StripGrid& sg, int& x0, int& y0, int& vc) {
+  const int b = (int)blockIdx.x;
+  const int r = b / sg.nx;
+  x0 = (b - r * sg.nx) * kStripW;
+  y0 = (r % sg.ny) * kStripH;
+  vc = r / sg.ny;
 }
 
-__device__ __forceinline__ float at(const float* p, int W, int H, int x, int y) {
-  return (x >= 0 && x < W && y >= 0 && y < H) ? p[(int64_t)y * W + x] : 0.f;
+// Orders a wave's own LDS writes and reads (the workgroup is that one wave, and a wave's LDS operations
+// execute in program order): a compiler barrier only.  __syncthreads() would also wait for every
+// outstanding global store of the wave, putting the output rows' store latency on the row loop.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_sched_barrier(0);  // also keeps the scheduler from hoisting later rows' loads (registers)
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
-                                                  int H, Win win, LossGrid lg, float* __restrict__ maps,
-                                                  double* __restrict__ partial) {
-  __shared__ float sx[kSide][kSide], sy[kSide][kSide];
-  __shared__ float hs[5][kSide][kTile];
-  __shared__ double red[2][4];
-  int bx, by, vc;  // vc = v * 3 + channel
-  if (!loss_tile(lg, bx, by, vc)) return;
-  const int64_t HW = (int64_t)W * H;
-  const float* X = img + vc * HW;
-  const float* Y = tgt + vc * HW;
-  const int ox = bx * kTile - kR, oy = by * kTile - kR;
-  for (int k = threadIdx.x; k < kSide * kSide; k += 256) {
-    const int ly = k / kSide, lx = k % kSide;
-    sx[ly][lx] = at(X, W, H, ox + lx, oy + ly);
-    sy[ly][lx] = at(Y, W, H, ox + lx, oy + ly);
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kSide * kTile; k += 256) {
-    const int ly = k / kTile, lx = k % kTile;
-    float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+// Loads and stores through buffer resources: an offset past the plane's end (kDrop) reads 0 (the zero
+// padding of the window) and drops a store (an output outside the image), so the row loop has no
+// branches and its only waits are for the loads of the row it is about to use, not for earlier stores.
+constexpr uint32_t kDrop = 0xfffffff0u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int64_t floats) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)(floats * 4), 0x00020000);
+}
+__device__ __forceinline__ float load_or_zero(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ void store_or_drop(__amdgpu_buffer_rsrc_t r, float v, uint32_t byte_off) {
+  // the builtin stores a 32-bit integer: pass the float's bits, not its value
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, byte_off, 0, 0);
+}
+
+// Byte offsets of row yy at columns x0 - 5 + lane (a) and x0 + 59 + lane for lane < 10 (b), kDrop
+// outside the image (or for a row past the strip, live = false).
+__device__ __forceinline__ void row_offsets(int W, int H, int x0, int yy, int lane, bool live, uint32_t& a,
+                                            uint32_t& b) {
+  const bool row = live && yy >= 0 && yy < H;
+  const int c0 = x0 - kR + lane, c1 = x0 - kR + kStripW + lane;
+  a = (row && c0 >= 0 && c0 < W) ? (uint32_t)((int64_t)yy * W + c0) * 4u : kDrop;
+  b = (row && lane < 2 * kR && c1 < W) ? (uint32_t)((int64_t)yy * W + c1) * 4u : kDrop;
+}
+
+// Vertical sum of ring slot values for the output whose newest input row sits in slot j (oldest first).
+template <int N, int J>
+__device__ __forceinline__ void vsum(const float (&ring)[kTaps][N], const Win& win, float (&o)[N]) {
 #pragma unroll
-    for (int a = 0; a < 11; ++a) {
-      const float xv = sx[ly][lx + a], yv = sy[ly][lx + a], g = win.g[a];
-      m0 = fmaf(g, xv, m0);
-      m1 = fmaf(g, yv, m1);
-      m2 = fmaf(g, xv * xv, m2);
-      m3 = fmaf(g, yv * yv, m3);
-      m4 = fmaf(g, xv * yv, m4);
-    }
-    hs[0][ly][lx] = m0; hs[1][ly][lx] = m1; hs[2][ly][lx] = m2; hs[3][ly][lx] = m3; hs[4][ly][lx] = m4;
-  }
-  __syncthreads();
-  const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
-  float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+  for (int q = 0; q < N; ++q) o[q] = 0.f;
 #pragma unroll
-  for (int b = 0; b < 11; ++b) {
-    const float g = win.g[b];
-    mx = fmaf(g, hs[0][ly + b][lx], mx);
-    my = fmaf(g, hs[1][ly + b][lx], my);
-    exx = fmaf(g, hs[2][ly + b][lx], exx);
-    eyy = fmaf(g, hs[3][ly + b][lx], eyy);
-    exy = fmaf(g, hs[4][ly + b][lx], exy);
+  for (int b = 0; b < kTaps; ++b) {
+    const int k = (J + 1 + b) % kTaps;
+#pragma unroll
+    for (int q = 0; q < N; ++q) o[q] = fmaf(win.g[b], ring[k][q], o[q]);
   }
-  const int px = bx * kTile + lx, py = by * kTile + ly;
-  double m_sum = 0, l1_sum = 0;
-  if (px < W && py < H) {
-    const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-    const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
-    const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
-    const float iB = 1.f / (B1 * B2);
-    const float m = A1 * A2 * iB;
-    const int64_t p = (int64_t)py * W + px;
-    float* mp = maps + (int64_t)vc * 3 * HW + p;
-    mp[0] = 2.f * my * (A2 - A1) * iB - 2.f * m * mx * (1.f / B1 - 1.f / B2);
-    mp[HW] = -m / B2;
-    mp[2 * HW] = 2.f * A1 * iB;
-    m_sum = m;
-    l1_sum = fabsf(sx[ly + kR][lx + kR] - sy[ly + kR][lx + kR]);
+}
+
+struct FwdStrip {
+  __amdgpu_buffer_rsrc_t rx, ry, rm;
+  int W, H, x0, y0, lane;
+  int64_t HW;
+  float xa[kAhead], xb[kAhead], ya[kAhead], yb[kAhead];  // the next kAhead rows, oldest first
+  float ring[kTaps][5];  // horizontal sums of the last 11 input rows, slot = row % 11
+  float cx[kTaps], cy[kTaps];  // the lane's own column of those rows
+  double m_sum, l1_sum;
+};
+
+// Loads input row rn of the strip into queue slot Q.
+template <int Q>
+__device__ __forceinline__ void fwd_load(FwdStrip& f, int rn) {
+  uint32_t oa, ob;
+  row_offsets(f.W, f.H, f.x0, f.y0 - kR + rn, f.lane, rn < kInRows, oa, ob);
+  f.xa[Q] = load_or_zero(f.rx, oa);
+  f.xb[Q] = load_or_zero(f.rx, ob);
+  f.ya[Q] = load_or_zero(f.ry, oa);
+  f.yb[Q] = load_or_zero(f.ry, ob);
+}
+
+template <int J, int Q>
+__device__ __forceinline__ void fwd_row(FwdStrip& f, float* sx, float* sy, const Win& win, int r) {
+  // r = input row index within the strip (y0 - 5 + r): ring slot J = r % 11, queue slot Q = r % 2
+  wave_lds_order();  // the previous row is no longer read
+  sx[f.lane] = f.xa[Q];
+  sy[f.lane] = f.ya[Q];
+  if (f.lane < 2 * kR) {
+    sx[kStripW + f.lane] = f.xb[Q];
+    sy[kStripW + f.lane] = f.yb[Q];
   }
-  // per-block sums in FP64, fixed order: butterfly within each wave, then the four waves in order
+  wave_lds_order();
+  fwd_load<Q>(f, r + kAhead);  // the slot is free again: the row two ahead
+  float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+#pragma unroll
+  for (int a = 0; a < kTaps; ++a) {
+    const float xv = sx[f.lane + a], yv = sy[f.lane + a], g = win.g[a];
+    m0 = fmaf(g, xv, m0);
+    m1 = fmaf(g, yv, m1);
+    m2 = fmaf(g, xv * xv, m2);
+    m3 = fmaf(g, yv * yv, m3);
+    m4 = fmaf(g, xv * yv, m4);
+  }
+  f.ring[J][0] = m0; f.ring[J][1] = m1; f.ring[J][2] = m2; f.ring[J][3] = m3; f.ring[J][4] = m4;
+  f.cx[J] = sx[f.lane + kR];
+  f.cy[J] = sy[f.lane + kR];
+}
+
+// Output row y0 + r - 10 from the ring (its newest input row in slot J).
+template <int J>
+__device__ __forceinline__ void fwd_out(FwdStrip& f, const Win& win, int r) {
+  float v[5];
+  vsum<5, J>(f.ring, win, v);
+  const float mx = v[0], my = v[1], exx = v[2], eyy = v[3], exy = v[4];
+  const int px = f.x0 + f.lane, py = f.y0 + r - 2 * kR;
+  const bool in = px < f.W && py < f.H;
+  const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
+  const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
+  const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+  // single-precision reciprocals (1 ulp) in place of IEEE divisions
+  const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
+  const float iB = iB1 * iB2;
+  const float m = A1 * A2 * iB;
+  const uint32_t o = (uint32_t)((int64_t)py * f.W + px) * 4u, hw = (uint32_t)f.HW * 4u;
+  store_or_drop(f.rm, 2.f * my * (A2 - A1) * iB - 2.f * m * mx * (iB1 - iB2), in ? o : kDrop);
+  store_or_drop(f.rm, -m * iB2, in ? o + hw : kDrop);
+  store_or_drop(f.rm, 2.f * A1 * iB, in ? o + 2u * hw : kDrop);
+  // the centre pixel is input row r - 5: slot J + 6 (mod 11)
+  constexpr int kc = (J + kR + 1) % kTaps;
+  f.m_sum += in ? (double)m : 0.0;
+  f.l1_sum += in ? (double)fabsf(f.cx[kc] - f.cy[kc]) : 0.0;
+}
+
+template <int J, int Q>
+__device__ __forceinline__ void fwd_step(FwdStrip& f, float* sx, float* sy, const Win& win, int r, bool out) {
+  fwd_row<J, Q>(f, sx, sy, win, r);
+  if (out) fwd_out<J>(f, win, r);
+}
+
+__global__ __launch_bounds__(64) void k_ssim_fwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
+                                                 int H, Win win, StripGrid sg, float* __restrict__ maps,
+                                                 double* __restrict__ partial) {
+  __shared__ float sx[kRowW], sy[kRowW];
+  FwdStrip f;
+  int vc;
+  strip_of_block(sg, f.x0, f.y0, vc);
+  f.W = W;
+  f.H = H;
+  f.lane = (int)threadIdx.x;
+  f.HW = (int64_t)W * H;
+  f.rx = plane_rsrc(img + vc * f.HW, f.HW);
+  f.ry = plane_rsrc(tgt + vc * f.HW, f.HW);
+  f.rm = plane_rsrc(maps + (int64_t)vc * 3 * f.HW, 3 * f.HW);
+  f.m_sum = f.l1_sum = 0.0;
+  fwd_load<0>(f, 0);
+  fwd_load<1>(f, 1);
+  // rows 0..10 fill the ring (the first output comes with row 10), then 22 rows per iteration, one output
+  // each; the ring slot is row % 11 and the queue slot row % 2, both fixed at every unrolled position
+  fwd_step<0, 0>(f, sx, sy, win, 0, false);
+  fwd_step<1, 1>(f, sx, sy, win, 1, false);
+  fwd_step<2, 0>(f, sx, sy, win, 2, false);
+  fwd_step<3, 1>(f, sx, sy, win, 3, false);
+  fwd_step<4, 0>(f, sx, sy, win, 4, false);
+  fwd_step<5, 1>(f, sx, sy, win, 5, false);
+  fwd_step<6, 0>(f, sx, sy, win, 6, false);
+  fwd_step<7, 1>(f, sx, sy, win, 7, false);
+  fwd_step<8, 0>(f, sx, sy, win, 8, false);
+  fwd_step<9, 1>(f, sx, sy, win, 9, false);
+  fwd_step<10, 0>(f, sx, sy, win, 10, true);
+#pragma nounroll
+  for (int r0 = kTaps; r0 < kInRows; r0 += 2 * kTaps) {
+    fwd_step<0, 1>(f, sx, sy, win, r0 + 0, true);
+    fwd_step<1, 0>(f, sx, sy, win, r0 + 1, true);
+    fwd_step<2, 1>(f, sx, sy, win, r0 + 2, true);
+    fwd_step<3, 0>(f, sx, sy, win, r0 + 3, true);
+    fwd_step<4, 1>(f, sx, sy, win, r0 + 4, true);
+    fwd_step<5, 0>(f, sx, sy, win, r0 + 5, true);
+    fwd_step<6, 1>(f, sx, sy, win, r0 + 6, true);
+    fwd_step<7, 0>(f, sx, sy, win, r0 + 7, true);
+    fwd_step<8, 1>(f, sx, sy, win, r0 + 8, true);
+    fwd_step<9, 0>(f, sx, sy, win, r0 + 9, true);
+    fwd_step<10, 1>(f, sx, sy, win, r0 + 10, true);
+    fwd_step<0, 0>(f, sx, sy, win, r0 + 11, true);
+    fwd_step<1, 1>(f, sx, sy, win, r0 + 12, true);
+    fwd_step<2, 0>(f, sx, sy, win, r0 + 13, true);
+    fwd_step<3, 1>(f, sx, sy, win, r0 + 14, true);
+    fwd_step<4, 0>(f, sx, sy, win, r0 + 15, true);
+    fwd_step<5, 1>(f, sx, sy, win, r0 + 16, true);
+    fwd_step<6, 0>(f, sx, sy, win, r0 + 17, true);
+    fwd_step<7, 1>(f, sx, sy, win, r0 + 18, true);
+    fwd_step<8, 0>(f, sx, sy, win, r0 + 19, true);
+    fwd_step<9, 1>(f, sx, sy, win, r0 + 20, true);
+    fwd_step<10, 0>(f, sx, sy, win, r0 + 21, true);
+  }
+  // per-wave sums in FP64, fixed order (butterfly)
+  double m_sum = f.m_sum, l1_sum = f.l1_sum;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     m_sum += __shfl_xor(m_sum, o, 64);
     l1_sum += __shfl_xor(l1_sum, o, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = m_sum;
-    red[1][threadIdx.x >> 6] = l1_sum;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t blk = ((int64_t)vc * lg.ty + by) * lg.tx + bx;
-    partial[2 * blk] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    partial[2 * blk + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  if (f.lane == 0) {
+    partial[2 * (int64_t)blockIdx.x] = m_sum;
+    partial[2 * (int64_t)blockIdx.x + 1] = l1_sum;
   }
 }
 
-__global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
-                                                  int H, Win win, LossGrid lg, float lambda,
-                                                  const float* __restrict__ maps, float* __restrict__ d_img,
-                                                  float* __restrict__ d_ssim) {
-  __shared__ float sm[3][kSide][kSide];
-  __shared__ float hs[3][kSide][kTile];
-  int bx, by, vc;
-  if (!loss_tile(lg, bx, by, vc)) return;
-  const int64_t HW = (int64_t)W * H;
-  const float* Mp = maps + (int64_t)vc * 3 * HW;
-  const int ox = bx * kTile - kR, oy = by * kTile - kR;
-  for (int k = threadIdx.x; k < kSide * kSide; k += 256) {
-    const int ly = k / kSide, lx = k % kSide;
-    sm[0][ly][lx] = at(Mp, W, H, ox + lx, oy + ly);
-    sm[1][ly][lx] = at(Mp + HW, W, H, ox + lx, oy + ly);
-    sm[2][ly][lx] = at(Mp + 2 * HW, W, H, ox + lx, oy + ly);
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kSide * kTile; k += 256) {
-    const int ly = k / kTile, lx = k % kTile;
-    float m0 = 0, m1 = 0, m2 = 0;
+struct BwdStrip {
+  __amdgpu_buffer_rsrc_t rm, rx, ry, rs, ri;
+  int W, H, x0, y0, lane;
+  int64_t HW;
+  float ninv, lambda;
+  float va[kAhead][3], vb[kAhead][3];  // the next kAhead rows of the three maps, oldest first
+  float xv[kAhead], yv[kAhead];        // image and target at those rows' output pixels
+  float ring[kTaps][3];
+};
+
+// Loads input row rn of the strip (three maps) and the image / target at its output pixel into slot k.
+template <int k>
+__device__ __forceinline__ void bwd_load(BwdStrip& f, int rn) {
+  uint32_t oa, ob;
+  row_offsets(f.W, f.H, f.x0, f.y0 - kR + rn, f.lane, rn < kInRows, oa, ob);
+  const uint32_t hw = (uint32_t)f.HW * 4u;
 #pragma unroll
-    for (int a = 0; a < 11; ++a) {
-      const float g = win.g[a];
-      m0 = fmaf(g, sm[0][ly][lx + a], m0);
-      m1 = fmaf(g, sm[1][ly][lx + a], m1);
-      m2 = fmaf(g, sm[2][ly][lx + a], m2);
-    }
-    hs[0][ly][lx] = m0; hs[1][ly][lx] = m1; hs[2][ly][lx] = m2;
+  for (int q = 0; q < 3; ++q) {
+    f.va[k][q] = load_or_zero(f.rm, oa == kDrop ? kDrop : oa + (uint32_t)q * hw);
+    f.vb[k][q] = load_or_zero(f.rm, ob == kDrop ? kDrop : ob + (uint32_t)q * hw);
   }
-  __syncthreads();
-  const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
-  const int px = bx * kTile + lx, py = by * kTile + ly;
-  if (!(px < W && py < H)) return;
-  float s0 = 0, s1 = 0, s2 = 0;
+  const int px = f.x0 + f.lane, pyn = f.y0 + rn - 2 * kR;
+  const bool ok = rn >= 2 * kR && rn < kInRows && px < f.W && pyn < f.H;
+  const uint32_t on = ok ? (uint32_t)((int64_t)pyn * f.W + px) * 4u : kDrop;
+  f.xv[k] = load_or_zero(f.rx, on);
+  f.yv[k] = load_or_zero(f.ry, on);
+}
+
+template <int J, int Q>
+__device__ __forceinline__ void bwd_step(BwdStrip& f, float (*sm)[kRowW], const Win& win, int r, bool out) {
+  wave_lds_order();
 #pragma unroll
-  for (int b = 0; b < 11; ++b) {
-    const float g = win.g[b];
-    s0 = fmaf(g, hs[0][ly + b][lx], s0);
-    s1 = fmaf(g, hs[1][ly + b][lx], s1);
-    s2 = fmaf(g, hs[2][ly + b][lx], s2);
+  for (int q = 0; q < 3; ++q) {
+    sm[q][f.lane] = f.va[Q][q];
+    if (f.lane < 2 * kR) sm[q][kStripW + f.lane] = f.vb[Q][q];
   }
-  const int64_t p = (int64_t)vc * HW + (int64_t)py * W + px;
-  const float xv = img[p], yv = tgt[p];
-  const float ninv = 1.f / (3.f * (float)HW);
-  const float dssim = ninv * (s0 + 2.f * xv * s1 + yv * s2);
-  const float d = xv - yv;
+  wave_lds_order();
+  const float xc = f.xv[Q], yc = f.yv[Q];  // this row's output pixel
+  bwd_load<Q>(f, r + kAhead);
+  float m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+  for (int a = 0; a < kTaps; ++a) {
+    const float g = win.g[a];
+    m0 = fmaf(g, sm[0][f.lane + a], m0);
+    m1 = fmaf(g, sm[1][f.lane + a], m1);
+    m2 = fmaf(g, sm[2][f.lane + a], m2);
+  }
+  f.ring[J][0] = m0; f.ring[J][1] = m1; f.ring[J][2] = m2;
+  if (!out) return;
+  float sv[3];
+  vsum<3, J>(f.ring, win, sv);
+  const int px = f.x0 + f.lane, py = f.y0 + r - 2 * kR;
+  const bool in = px < f.W && py < f.H;
+  const uint32_t o = in ? (uint32_t)((int64_t)py * f.W + px) * 4u : kDrop;
+  const float dssim = f.ninv * (sv[0] + 2.f * xc * sv[1] + yc * sv[2]);
+  const float d = xc - yc;
   const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-  d_ssim[p] = -lambda * dssim;
-  d_img[p] = (1.f - lambda) * sgn * ninv - lambda * dssim;
+  store_or_drop(f.rs, -f.lambda * dssim, o);
+  store_or_drop(f.ri, (1.f - f.lambda) * sgn * f.ninv - f.lambda * dssim, o);
+}
+
+__global__ __launch_bounds__(64) void k_ssim_bwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
+                                                 int H, Win win, StripGrid sg, float lambda,
+                                                 const float* __restrict__ maps, float* __restrict__ d_img,
+                                                 float* __restrict__ d_ssim) {
+  __shared__ float sm[3][kRowW];
+  BwdStrip f;
+  int vc;
+  strip_of_block(sg, f.x0, f.y0, vc);
+  f.W = W;
+  f.H = H;
+  f.lane = (int)threadIdx.x;
+  f.HW = (int64_t)W * H;
+  f.ninv = 1.f / (3.f * (float)f.HW);
+  f.lambda = lambda;
+  f.rm = plane_rsrc(maps + (int64_t)vc * 3 * f.HW, 3 * f.HW);
+  f.rx = plane_rsrc(img + vc * f.HW, f.HW);
+  f.ry = plane_rsrc(tgt + vc * f.HW, f.HW);
+  f.rs = plane_rsrc(d_ssim + vc * f.HW, f.HW);
+  f.ri = plane_rsrc(d_img + vc * f.HW, f.HW);
+  bwd_load<0>(f, 0);
+  bwd_load<1>(f, 1);
+  bwd_step<0, 0>(f, sm, win, 0, false);
+  bwd_step<1, 1>(f, sm, win, 1, false);
+  bwd_step<2, 0>(f, sm, win, 2, false);
+  bwd_step<3, 1>(f, sm, win, 3, false);
+  bwd_step<4, 0>(f, sm, win, 4, false);
+  bwd_step<5, 1>(f, sm, win, 5, false);
+  bwd_step<6, 0>(f, sm, win, 6, false);
+  bwd_step<7, 1>(f, sm, win, 7, false);
+  bwd_step<8, 0>(f, sm, win, 8, false);
+  bwd_step<9, 1>(f, sm, win, 9, false);
+  bwd_step<10, 0>(f, sm, win, 10, true);
+#pragma nounroll
+  for (int r0 = kTaps; r0 < kInRows; r0 += 2 * kTaps) {
+    bwd_step<0, 1>(f, sm, win, r0 + 0, true);
+    bwd_step<1, 0>(f, sm, win, r0 + 1, true);
+    bwd_step<2, 1>(f, sm, win, r0 + 2, true);
+    bwd_step<3, 0>(f, sm, win, r0 + 3, true);
+    bwd_step<4, 1>(f, sm, win, r0 + 4, true);
+    bwd_step<5, 0>(f, sm, win, r0 + 5, true);
+    bwd_step<6, 1>(f, sm, win, r0 + 6, true);
+    bwd_step<7, 0>(f, sm, win, r0 + 7, true);
+    bwd_step<8, 1>(f, sm, win, r0 + 8, true);
+    bwd_step<9, 0>(f, sm, win, r0 + 9, true);
+    bwd_step<10, 1>(f, sm, win, r0 + 10, true);
+    bwd_step<0, 0>(f, sm, win, r0 + 11, true);
+    bwd_step<1, 1>(f, sm, win, r0 + 12, true);
+    bwd_step<2, 0>(f, sm, win, r0 + 13, true);
+    bwd_step<3, 1>(f, sm, win, r0 + 14, true);
+    bwd_step<4, 0>(f, sm, win, r0 + 15, true);
+    bwd_step<5, 1>(f, sm, win, r0 + 16, true);
+    bwd_step<6, 0>(f, sm, win, r0 + 17, true);
+    bwd_step<7, 1>(f, sm, win, r0 + 18, true);
+    bwd_step<8, 0>(f, sm, win, r0 + 19, true);
+    bwd_step<9, 1>(f, sm, win, r0 + 20, true);
+    bwd_step<10, 0>(f, sm, win, r0 + 21, true);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ partial, int64_t blocks_per_view,
@@ -192,7 +376,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
         red[0][threadIdx.x] += red[0][threadIdx.x + off];
         red[1][threadIdx.x] += red[1][threadIdx.x + off];
       }
-      __syncthreads();
+      wave_lds_order();
     }
     if (threadIdx.x == 0) {
       const double ssim = red[0][0] / (3.0 * HW), l1 = red[1][0] / (3.0 * HW);
@@ -207,11 +391,11 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 }  // namespace cgv2
 
 size_t cgv2_loss_ws_layout(int W, int H, int V, size_t* off) {
-  const int64_t bx = (W + 15) / 16, by = (H + 15) / 16;
+  const int64_t nx = (W + cgv2::kStripW - 1) / cgv2::kStripW, ny = (H + cgv2::kStripH - 1) / cgv2::kStripH;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
   off[0] = take(sizeof(float) * 9 * (size_t)W * H * V);     // partial maps [V][3][3][H][W]
-  off[1] = take(sizeof(double) * 2 * (size_t)(bx * by * 3 * V));
+  off[1] = take(sizeof(double) * 2 * (size_t)(nx * ny * 3 * V));  // per-wave sums
   return o;
 }
 
@@ -225,15 +409,14 @@ hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, in
   double g[11], gs = 0;
   for (int a = -5; a <= 5; ++a) { g[a + 5] = exp(-(double)(a * a) / (2 * 1.5 * 1.5)); gs += g[a + 5]; }
   for (int a = 0; a < 11; ++a) win.g[a] = (float)(g[a] / gs);
-  cgv2::LossGrid lg;
-  lg.tx = (W + 15) / 16;
-  lg.ty = (H + 15) / 16;
-  lg.band = (lg.tx + 7) / 8;
-  const unsigned blocks = (unsigned)(8 * lg.band * lg.ty * 3 * V);
-  hipLaunchKernelGGL(cgv2::k_ssim_fwd, dim3(blocks), dim3(256), 0, st, img, tgt, W, H, win, lg, maps, partial);
-  hipLaunchKernelGGL(cgv2::k_ssim_bwd, dim3(blocks), dim3(256), 0, st, img, tgt, W, H, win, lg, lambda, maps, d_img,
+  cgv2::StripGrid sg;
+  sg.nx = (W + cgv2::kStripW - 1) / cgv2::kStripW;
+  sg.ny = (H + cgv2::kStripH - 1) / cgv2::kStripH;
+  const unsigned blocks = (unsigned)(sg.nx * sg.ny * 3 * V);
+  hipLaunchKernelGGL(cgv2::k_ssim_fwd, dim3(blocks), dim3(64), 0, st, img, tgt, W, H, win, sg, maps, partial);
+  hipLaunchKernelGGL(cgv2::k_ssim_bwd, dim3(blocks), dim3(64), 0, st, img, tgt, W, H, win, sg, lambda, maps, d_img,
                      d_ssim);
-  hipLaunchKernelGGL(cgv2::k_loss_final, dim3(1), dim3(256), 0, st, partial, (int64_t)lg.tx * lg.ty * 3, V,
+  hipLaunchKernelGGL(cgv2::k_loss_final, dim3(1), dim3(256), 0, st, partial, (int64_t)sg.nx * sg.ny * 3, V,
                      (int64_t)W * H, lambda, loss);
   return hipGetLastError();
 }
