@@ -82,11 +82,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ 
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-// pass 1 of the surfel scan: per-chunk sums of the tile counts and of the visible flags
+// pass 1 of the surfel scan: per-chunk sums of the tile counts and of the visible flags; the workgroups
+// also zero the nz tile counters (and the big-list count after them), which k_stage uses two launches later
 __global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __restrict__ rect, int64_t m,
                                                             uint64_t* __restrict__ sums_cnt,
-                                                            uint64_t* __restrict__ sums_vis) {
+                                                            uint64_t* __restrict__ sums_vis,
+                                                            uint32_t* __restrict__ zero, int64_t nz) {
   __shared__ uint64_t lds[2][kScanBlock];
+  for (int64_t z = (int64_t)blockIdx.x * kScanBlock + threadIdx.x; z < nz; z += (int64_t)gridDim.x * kScanBlock)
+    zero[z] = 0u;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint64_t c = 0, f = 0;
   for (int k = 0; k < kScanItems; ++k) {
@@ -506,13 +510,11 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   uint64_t* stk = (uint64_t*)(w + off[5]);
   uint2* stp = (uint2*)(w + off[6]);
   uint32_t* soff = (uint32_t*)(w + off[7]);
-  // tile counters and the big-list count
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)std::min<int64_t>((m + 256) / 256, 65535)), dim3(256), 0, st,
-                     cnt, m + 1, 0u);
   if (n > 0) {
     // surfel offsets, visible lists (consumed by the staging here and by the reverse pass), total and
-    // overflow check
-    hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis);
+    // overflow check; the tile counters and the big-list count are zeroed on the way
+    hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis,
+                       cnt, m + 1);
     hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
     hipLaunchKernelGGL(k_surfel_apply, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, n, sums_cnt,
                        sums_vis, totals, soff, p.visible, p.visible_start, V, b.capacity, b.status, b.needed);
@@ -521,6 +523,8 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
                        p.visible, p.visible_start, soff, cnt, stp, stk, b.status);
   } else {
     // no surfels: empty lists, zero intersections
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)std::min<int64_t>((m + 256) / 256, 65535)), dim3(256), 0, st,
+                       cnt, m + 1, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, p.visible_start, (int64_t)V + 1, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, soff, (int64_t)1, 0u);
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(256), 0, st, b.needed, (int64_t)1, (int64_t)0);

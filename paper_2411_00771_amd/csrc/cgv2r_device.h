@@ -184,6 +184,14 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
     p[i] = v;
 }
 
+// Zeroes count floats of a and of b (either may be null) in one launch.
+__global__ __launch_bounds__(256) inline void k_zero2(float* a, float* b, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    if (a) a[i] = 0.f;
+    if (b) b[i] = 0.f;
+  }
+}
+
 // Exclusive scan over a workgroup of kThreads threads (a multiple of 64); lds holds kThreads / 64
 // values; 'total' receives the workgroup sum.  Every thread of the workgroup must call it.
 template <int kThreads, typename T>

@@ -296,11 +296,16 @@ __device__ __forceinline__ void bwd_step(BwdStrip& f, float (*sm)[kRowW], const 
   store_or_drop(f.ri, (1.f - f.lambda) * sgn * f.ninv - f.lambda * dssim, o);
 }
 
+__device__ __noinline__ void loss_final(const double* __restrict__ partial, int64_t blocks_per_view, int V, int64_t HW,
+                                        float lambda, float* __restrict__ loss);
+
 __global__ __launch_bounds__(64) void k_ssim_bwd(const float* __restrict__ img, const float* __restrict__ tgt, int W,
                                                  int H, Win win, StripGrid sg, float lambda,
                                                  const float* __restrict__ maps, float* __restrict__ d_img,
-                                                 float* __restrict__ d_ssim) {
+                                                 float* __restrict__ d_ssim, const double* __restrict__ partial,
+                                                 int V, float* __restrict__ loss) {
   __shared__ float sm[3][kRowW];
+  if (blockIdx.x == 0) loss_final(partial, (int64_t)sg.nx * sg.ny * 3, V, (int64_t)W * H, lambda, loss);
   BwdStrip f;
   int vc;
   strip_of_block(sg, f.x0, f.y0, vc);
@@ -355,36 +360,31 @@ __global__ __launch_bounds__(64) void k_ssim_bwd(const float* __restrict__ img, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ partial, int64_t blocks_per_view,
-                                                    int V, int64_t HW, float lambda, float* __restrict__ loss) {
-  __shared__ double red[2][256];
+// The loss values of every view from the forward's per-wave sums, in a fixed order: run by the first
+// workgroup of k_ssim_bwd (the forward has completed by then).
+__device__ __noinline__ void loss_final(const double* __restrict__ partial, int64_t blocks_per_view, int V, int64_t HW,
+                                        float lambda, float* __restrict__ loss) {
+  const int lane = (int)threadIdx.x;
   for (int v = 0; v < V; ++v) {
-    // fixed summation order per thread; unrolled so that eight loads are in flight
     double a = 0, b = 0;
     const double2* pv = (const double2*)partial + v * blocks_per_view;
-#pragma unroll 8
-    for (int64_t k = threadIdx.x; k < blocks_per_view; k += 256) {
+#pragma unroll 4
+    for (int64_t k = lane; k < blocks_per_view; k += 64) {
       const double2 q = pv[k];
       a += q.x;
       b += q.y;
     }
-    red[0][threadIdx.x] = a;
-    red[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + off];
-        red[1][threadIdx.x] += red[1][threadIdx.x + off];
-      }
-      wave_lds_order();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      b += __shfl_xor(b, o, 64);
     }
-    if (threadIdx.x == 0) {
-      const double ssim = red[0][0] / (3.0 * HW), l1 = red[1][0] / (3.0 * HW);
+    if (lane == 0) {
+      const double ssim = a / (3.0 * HW), l1 = b / (3.0 * HW);
       loss[3 * v] = (float)((1.0 - lambda) * l1 + lambda * (1.0 - ssim));
       loss[3 * v + 1] = (float)l1;
       loss[3 * v + 2] = (float)ssim;
     }
-    __syncthreads();
   }
 }
 
@@ -415,8 +415,6 @@ hipError_t cgv2_launch_loss(const float* img, const float* tgt, int V, int W, in
   const unsigned blocks = (unsigned)(sg.nx * sg.ny * 3 * V);
   hipLaunchKernelGGL(cgv2::k_ssim_fwd, dim3(blocks), dim3(64), 0, st, img, tgt, W, H, win, sg, maps, partial);
   hipLaunchKernelGGL(cgv2::k_ssim_bwd, dim3(blocks), dim3(64), 0, st, img, tgt, W, H, win, sg, lambda, maps, d_img,
-                     d_ssim);
-  hipLaunchKernelGGL(cgv2::k_loss_final, dim3(1), dim3(256), 0, st, partial, (int64_t)sg.nx * sg.ny * 3, V,
-                     (int64_t)W * H, lambda, loss);
+                     d_ssim, partial, V, loss);
   return hipGetLastError();
 }
