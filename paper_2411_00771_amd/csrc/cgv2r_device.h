@@ -184,11 +184,12 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t count, T v) {
     p[i] = v;
 }
 
-// Zeroes count floats of a and of b (either may be null) in one launch.
-__global__ __launch_bounds__(256) inline void k_zero2(float* a, float* b, int64_t count) {
+// Zeroes count elements of a and of b (either may be null) in one launch.
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero2(T* a, T* b, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    if (a) a[i] = 0.f;
-    if (b) b[i] = 0.f;
+    if (a) a[i] = T(0);
+    if (b) b[i] = T(0);
   }
 }
 

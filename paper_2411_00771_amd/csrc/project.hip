@@ -561,7 +561,7 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
   const int64_t rows = (int64_t)cams.count * 2 * n;
   const unsigned fill_blocks = (unsigned)std::min<int64_t>((rows + 255) / 256, 65535);
   if (g.g_view_total || g.g_view_ssim)
-    hipLaunchKernelGGL(cgv2::k_zero2, dim3(fill_blocks), dim3(256), 0, st,
+    hipLaunchKernelGGL(cgv2::k_zero2<float>, dim3(fill_blocks), dim3(256), 0, st,
                        g.g_view_total ? g.g_view_total + (int64_t)cams.v0 * 2 * n : nullptr,
                        g.g_view_ssim ? g.g_view_ssim + (int64_t)cams.v0 * 2 * n : nullptr, rows);
   for (int lv = 0; lv < cams.count; ++lv) {
