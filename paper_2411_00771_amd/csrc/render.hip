@@ -815,7 +815,7 @@ __global__ __launch_bounds__(256) void k_zero_visible(const uint32_t* __restrict
 
 // Heavy tiles split into quadrant blocks: 1 / kSplitDiv of a launch's tiles, at most kSplitMax.
 #ifndef CGV2_SPLIT_DIV
-#define CGV2_SPLIT_DIV 16
+#define CGV2_SPLIT_DIV 24
 #endif
 constexpr int kSplitDiv = CGV2_SPLIT_DIV;
 constexpr int kSplitMax = 1024;

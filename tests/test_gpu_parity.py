@@ -267,6 +267,39 @@ def test_densify_matches_oracle(tiny, cuda):
             assert np.array_equal(c[:6], r["counters"][:6])
 
 
+@pytest.mark.parametrize("V", [3, 12])
+def test_densify_multi_view_matches_oracle(cuda, V):
+    # V views in one call against the oracle applied view after view, on synthetic gradients and masks
+    import torch
+    from paper_2411_00771_amd import raster
+    n = 5000
+    sc = scenes.tiny_scene(9, n)
+    params = raster.Params.from_scene(sc)
+    eng = raster.Engine(n, 64, 64, V, capacity=1 << 12)
+    rng = np.random.default_rng(V)
+    flags = ((rng.random((V, n)) < 0.6) * 1 + (rng.random((V, n)) < 0.1) * 32).astype(np.uint8)
+    radius = rng.uniform(0, 20, (V, n)).astype(np.float32)
+    eng.flags.copy_(torch.from_numpy(flags.reshape(-1)))
+    eng.radius.copy_(torch.from_numpy(radius.reshape(-1)))
+    g = raster.Grads(params, V)
+    gt = rng.normal(0, 1e-5, (V, 2, n)).astype(np.float32)
+    gs = (rng.normal(0, 3e-6, (V, 2, n)) * rng.uniform(0.2, 1.0, (V, 1, 1))).astype(np.float32)
+    g.g_view_total.copy_(torch.from_numpy(gt))
+    g.g_view_ssim.copy_(torch.from_numpy(gs))
+    st = raster.DensifyState(n, V)
+    eng.densify(params, g, st, omega=0.9, eta_min=0.05, grad_threshold=2e-6)
+    torch.cuda.synchronize()
+    ost = oracle.new_densify_state(n)
+    for v in range(V):
+        r = oracle.densify_stats(gt[v].T, gs[v].T, (flags[v] & 1) > 0, radius[v], sc.log_scale, ost, 0.9, 0.05, 2e-6,
+                                 lowpass=(flags[v] & 32) > 0)
+        assert abs(st.scale[v].item() / r["scale"] - 1) <= 1e-6, v
+    assert np.allclose(st.accum_dgd.cpu().numpy(), ost["accum_dgd"], rtol=1e-5, atol=1e-12)
+    assert np.allclose(st.accum_total.cpu().numpy(), ost["accum_total"], rtol=1e-5, atol=1e-12)
+    assert np.array_equal(st.denom.cpu().numpy(), ost["denom"])
+    assert np.array_equal(st.max_radius.cpu().numpy(), ost["max_radius"].astype(np.float32))
+
+
 def test_multi_view_batch_equals_single_views(cuda):
     import torch
     w = scenes.workload(0)
