@@ -33,12 +33,18 @@ struct StripGrid {
   int nx, ny;
 };
 
-__device__ __forceinline__ void strip_of_block(const StripGrid& sg, int& x0, int& y0, int& vc) {
-  const int b = (int)blockIdx.x;
+// Hardware sends workgroup b to XCD b % 8: XCD x takes the x-th contiguous eighth of the strips (row-major
+// over strip columns, then strip rows, then planes), so the halo columns and rows that neighbouring
+// strips share are fetched into one L2.  Blocks past the last full round of 8 map to themselves.
+// Returns the strip index (the slot of its per-wave sums).
+__device__ __forceinline__ int strip_of_block(const StripGrid& sg, int& x0, int& y0, int& vc) {
+  const uint32_t nb = gridDim.x, full = nb - nb % 8u, bb = blockIdx.x;
+  const int b = (int)(bb < full ? (bb % 8u) * (full / 8u) + bb / 8u : bb);
   const int r = b / sg.nx;
   x0 = (b - r * sg.nx) * kStripW;
   y0 = (r % sg.ny) * kStripH;
   vc = r / sg.ny;
+  return b;
 }
 
 // Orders a wave's own LDS writes and reads (the workgroup is that one wave, and a wave's LDS operations
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(64) void k_ssim_fwd(const float* __restrict__ img, 
   __shared__ float sx[kRowW], sy[kRowW];
   FwdStrip f;
   int vc;
-  strip_of_block(sg, f.x0, f.y0, vc);
+  const int strip = strip_of_block(sg, f.x0, f.y0, vc);
   f.W = W;
   f.H = H;
   f.lane = (int)threadIdx.x;
@@ -230,8 +236,8 @@ __global__ __launch_bounds__(64) void k_ssim_fwd(const float* __restrict__ img, 
     l1_sum += __shfl_xor(l1_sum, o, 64);
   }
   if (f.lane == 0) {
-    partial[2 * (int64_t)blockIdx.x] = m_sum;
-    partial[2 * (int64_t)blockIdx.x + 1] = l1_sum;
+    partial[2 * (int64_t)strip] = m_sum;
+    partial[2 * (int64_t)strip + 1] = l1_sum;
   }
 }
 
