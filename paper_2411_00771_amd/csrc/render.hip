@@ -79,6 +79,12 @@ __device__ __forceinline__ uint32_t reach_quadrants(uint32_t m, const float4& q0
 // without it the quadrants the surfel cannot reach are dropped by reach_quadrants.
 __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* rec, int64_t vn, int64_t n, uint32_t id,
                                              int ox, int oy, const uint8_t* qmask, uint32_t idx) {
+  // an entry no pixel of the forward took reaches no quadrant here: its record is not read at all
+  const uint32_t qm = qmask ? qmask[idx] : 0xfu;
+  if (qm == 0u) {
+    s.qm[lane] = 0u;
+    return;
+  }
   // an id outside [0, n) (never produced by the binning) stages a record that reaches no quadrant
   const bool valid = (int64_t)id < n;
   const float4* r = (const float4*)(rec + (size_t)(vn + (valid ? id : 0u)) * kRec);
@@ -101,7 +107,7 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
     const int x0 = 8 * (k & 1), y0 = 8 * (k >> 1);
     if (i0 <= x0 + 7 && i1 >= x0 && j0 <= y0 + 7 && j1 >= y0) m |= 1u << k;
   }
-  if (qmask) m &= qmask[idx];
+  if (qmask) m &= qm;
   else if (m) m = reach_quadrants(m, q0, q1, r2.z, r4.w);
   s.qm[lane] = valid ? m : 0u;
 }
