@@ -118,11 +118,15 @@ typedef struct {
 } cgv2_proj;
 
 /* Tile bins.  ranges[V * tiles + 1]: list of tile t in view v is ids[ranges[v*tiles + t] ..
- * ranges[v*tiles + t + 1]), ordered front to back by (float32 bits of z_c, id).
- * *status is set to 1 when the intersections exceed 'capacity' (sticky: the library never
- * clears it; the caller zeroes it before the first call).  *needed receives the total number
- * of intersections of the call.  While *status != 0, bins are invalid, render calls write
- * nothing and the caller must rerun with capacity >= *needed.
+ * ranges[v*tiles + t + 1]), ordered front to back by (float32 bits of z_c, id).  A surfel is listed in
+ * the tiles of its rect where its alpha >= 1/255 region can reach a pixel sample: some point of the
+ * tile's pixel-sample box, padded by 1/64 px, has min(rho_3d, rho_2d) <= k^2 (1 + 2e-3) + 2e-3 (every
+ * pixel that can blend the surfel keeps it; Sec. 3.1 cutoff).
+ * The staging holds one slot per tile of every rect: 'capacity' and *needed count those slots.
+ * *status is set to 1 when they exceed 'capacity' (sticky: the library never clears it; the caller
+ * zeroes it before the first call).  *needed receives the total number of rect slots of the call.
+ * While *status != 0, bins are invalid, render calls write nothing and the caller must rerun with
+ * capacity >= *needed.
  * order (optional, [V * tiles]): the render calls' launch order.  When non-NULL, cgv2_bin_sort writes
  * it and the render calls (forward, count, backward, contribution) launch the tiles of each chunk of up
  * to 32 views heaviest first: order[32 c tiles + i] = the i-th tile (local index v' tiles + t within
