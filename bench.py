@@ -505,11 +505,13 @@ def main():
 
     # per-call split with events between all calls (separate pass)
     tot = np.zeros(len(names))
+    per_step = []
     for k in range(args.breakdown_steps):
         ev = events(range(len(names) + 1))
         step(k, ev)
         torch.cuda.synchronize()
         tot += [ev[i].elapsed_time(ev[i + 1]) for i in range(len(names))]
+        per_step.append(ev[0].elapsed_time(ev[len(names)]))
     split = {nm: tot[i] / max(args.breakdown_steps, 1) for i, nm in enumerate(names)}
     log("[bench] split (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in split.items()))
 
@@ -546,6 +548,9 @@ def main():
                    "sh_degree": sc.sh_degree, "step": "project+bin_sort+render_fwd+loss+render_bwd+project_bwd+densify"},
         "mpix_per_s": round(ips * W * H / 1e6, 2),
         "split_ms": {k: round(v, 4) for k, v in split.items()},
+        # one step per view of the 16, each synchronized on its own (the breakdown pass)
+        "step_ms_percentiles": ({f"p{q}": round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)}
+                                if per_step else None),
         "pairs_per_view": {"evaluated": int(mean_counts[0]), "contributing": int(mean_counts[1]),
                            "reverse_walked": int(mean_counts[2])},
         "intersections_max": int(need),

@@ -129,9 +129,10 @@ def test_loss_matches_oracle(tiny, cuda):
     assert np.abs(ds - ref["d_ssim"]).max() <= 1e-4 * np.abs(ref["d_ssim"]).max()
 
 
-@pytest.mark.parametrize("W,H", [(150, 37), (64, 16), (65, 17), (1, 1)])
+@pytest.mark.parametrize("W,H", [(150, 37), (64, 16), (65, 17), (1, 1), (64, 45), (65, 46), (3, 200), (300, 2)])
 def test_loss_ragged_multi_view(cuda, W, H):
-    """Loss tiles of 64 x 16 over sizes that leave partial tiles (and a single pixel), two views per call."""
+    """Loss strips of 64 columns x 45 rows over sizes that leave partial strips (and a single pixel), two
+    views per call (the per-strip sums of both views are kept apart whatever XCD runs each strip)."""
     import torch
     from paper_2411_00771_amd import raster
     rng = np.random.default_rng(W * 100 + H)
