@@ -91,11 +91,12 @@ def test_aerial_loss_full_size(aerial, cuda):
     import torch
     v = aerial["views"][1]
     eng, cam = v["eng"], v["cam"]
+    # a synthetic rendering of the view's size stands in for the image, given to both sides
     tgt = scenes.random_target(5, cam.width, cam.height)
-    lv = eng.loss(torch.from_numpy(tgt).to(cuda)[None])
+    img = scenes.random_target(6, cam.width, cam.height)
+    lv = eng.loss(torch.from_numpy(tgt).to(cuda)[None], img=torch.from_numpy(img).to(cuda)[None].contiguous())
     torch.cuda.synchronize()
-    img = eng.rgb[0].cpu().numpy().astype(np.float64)
-    ref = oracle.ssim_loss(img, tgt)
+    ref = oracle.ssim_loss(img.astype(np.float64), tgt)
     assert abs(lv[0, 0].item() - ref["loss"]) <= 1e-5 * abs(ref["loss"])
     dt = eng.d_img[0].cpu().numpy()
     assert np.abs(dt - ref["d_total"]).max() <= 1e-4 * np.abs(ref["d_total"]).max()
@@ -133,8 +134,6 @@ def test_aerial_backward_on_sampled_tiles_and_densify(aerial, cuda):
     eng.forward(params, cs)
     g = raster.Grads(params, 1)
     eng.backward(params, cs, g, **{k: torch.from_numpy(a).to(cuda)[None].contiguous() for k, a in up.items()})
-    st = raster.DensifyState(sc.n)
-    eng.densify(params, g, st)
     torch.cuda.synchronize()
     tmask = np.zeros(len(off) - 1, np.uint8)
     tmask[tiles] = 1
@@ -148,15 +147,30 @@ def test_aerial_backward_on_sampled_tiles_and_densify(aerial, cuda):
     gt = oracle.viewspace_grad(po["M"], og["M"], W, H)
     grad_close("g_view_total", g.g_view_total[0].cpu().numpy().T, gt)
     os_ = oracle.render_bwd(po, cam, off, oids, d_rgb=up64["d_rgb_ssim"], tile_mask=tmask)
-    grad_close("g_view_ssim", g.g_view_ssim[0].cpu().numpy().T, oracle.viewspace_grad(po["M"], os_["M"], W, H))
-    # densify on the GPU's own view-space gradients (full size, 1 M surfels)
-    P = fetch_proj(eng)
+    gs = oracle.viewspace_grad(po["M"], os_["M"], W, H)
+    grad_close("g_view_ssim", g.g_view_ssim[0].cpu().numpy().T, gs)
+    # densify at full size (1 M surfels) on the oracle's view-space gradients, visibility and radii,
+    # rounded to FP32 and given to both sides
+    gt32, gs32 = gt.astype(np.float32), gs.astype(np.float32)
+    flags = po["flags"].astype(np.uint8)
+    radius = po["radius"].astype(np.float32)
+    saved = eng.flags.clone(), eng.radius.clone()
+    g.g_view_total[0].copy_(torch.from_numpy(np.ascontiguousarray(gt32.T)))
+    g.g_view_ssim[0].copy_(torch.from_numpy(np.ascontiguousarray(gs32.T)))
+    eng.flags.view(-1, sc.n)[0].copy_(torch.from_numpy(flags))
+    eng.radius.view(-1, sc.n)[0].copy_(torch.from_numpy(radius))
+    st = raster.DensifyState(sc.n)
+    eng.densify(params, g, st)
+    torch.cuda.synchronize()
+    eng.flags.copy_(saved[0])
+    eng.radius.copy_(saved[1])
     ost = oracle.new_densify_state(sc.n)
-    r = oracle.densify_stats(g.g_view_total[0].cpu().numpy().T.astype(np.float64),
-                             g.g_view_ssim[0].cpu().numpy().T.astype(np.float64), (P["flags"][0] & 1) > 0,
-                             P["radius"][0], sc.log_scale, ost)
+    r = oracle.densify_stats(gt32.astype(np.float64), gs32.astype(np.float64), (flags & 1) > 0, radius,
+                             sc.log_scale, ost, lowpass=(flags & 32) > 0)
     assert abs(st.scale[0].item() / r["scale"] - 1) <= 1e-6
     assert np.allclose(st.accum_dgd.cpu().numpy(), ost["accum_dgd"], rtol=1e-5, atol=1e-20)
     assert np.array_equal(st.denom.cpu().numpy(), ost["denom"])
+    assert np.array_equal(st.max_radius.cpu().numpy(), ost["max_radius"].astype(np.float32))
     assert int(st.counters[0].item()) == int(r["counters"][0])
     assert int(st.counters[2].item()) == int(r["counters"][2])
+    assert int(st.counters[4].item()) == int(r["counters"][4])

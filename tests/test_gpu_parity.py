@@ -235,25 +235,34 @@ def test_render_bwd_matches_oracle(tiny, cuda):
 
 
 def test_densify_matches_oracle(tiny, cuda):
+    # densify on the oracle's view-space gradients, visibility and radii of the tiny view, rounded to FP32
+    # and given to both sides
     import torch
     from paper_2411_00771_amd import raster
     eng, params, cs = tiny["eng"], tiny["params"], tiny["cs"]
-    eng.forward(params, cs)
+    po = tiny["po"]
     up = _upstream(tiny, seed=5)
+    ref = oracle.backward_view(tiny["sc"], tiny["cam"], po, tiny["off"], tiny["ids"],
+                               {k: v.astype(np.float64) for k, v in up.items()})
+    gt = ref["g_total"].astype(np.float32)
+    gs = ref["g_ssim"].astype(np.float32)
+    flags = po["flags"].astype(np.uint8)
+    radius = po["radius"].astype(np.float32)
+    vis = (flags & 1) > 0
+    lp = (flags & 32) > 0
+    assert vis.sum() > 100 and np.abs(gs[vis]).sum() > 0
     g = raster.Grads(params, 1)
-    t = {k: torch.from_numpy(v).to(cuda)[None].contiguous() for k, v in up.items()}
-    eng.backward(params, cs, g, **t)
+    g.g_view_total[0].copy_(torch.from_numpy(np.ascontiguousarray(gt.T)))
+    g.g_view_ssim[0].copy_(torch.from_numpy(np.ascontiguousarray(gs.T)))
+    eng.flags.view(-1, params.n)[0].copy_(torch.from_numpy(flags))
+    eng.radius.view(-1, params.n)[0].copy_(torch.from_numpy(radius))
     st = raster.DensifyState(params.n)
     ost = oracle.new_densify_state(params.n)
-    P = fetch_proj(eng)
-    vis = (P["flags"][0] & 1) > 0
-    lp = (P["flags"][0] & 32) > 0
     for call in range(2):
         eng.densify(params, g, st, omega=0.9, eta_min=0.05, grad_threshold=2e-6)
         torch.cuda.synchronize()
-        gt = g.g_view_total[0].cpu().numpy().T.astype(np.float64)
-        gs = g.g_view_ssim[0].cpu().numpy().T.astype(np.float64)
-        r = oracle.densify_stats(gt, gs, vis, P["radius"][0], tiny["sc"].log_scale, ost, 0.9, 0.05, 2e-6, lowpass=lp)
+        r = oracle.densify_stats(gt.astype(np.float64), gs.astype(np.float64), vis, radius, tiny["sc"].log_scale,
+                                 ost, 0.9, 0.05, 2e-6, lowpass=lp)
         assert abs(st.scale[0].item() / r["scale"] - 1) <= 1e-6
         assert np.allclose(st.accum_dgd.cpu().numpy(), ost["accum_dgd"], rtol=1e-5, atol=1e-12)
         assert np.allclose(st.accum_total.cpu().numpy(), ost["accum_total"], rtol=1e-5, atol=1e-12)
@@ -266,6 +275,9 @@ def test_densify_matches_oracle(tiny, cuda):
         c = st.counters.cpu().numpy()
         if not near.any():
             assert np.array_equal(c[:6], r["counters"][:6])
+    # the engine's own projection again for the tests that follow
+    eng.forward(params, cs)
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("V", [3, 12])

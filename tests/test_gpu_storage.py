@@ -56,12 +56,15 @@ def test_vq_assign_and_init(cuda, D, K):
     xt, rt = _t(x), _t(rows.view(np.int32))
     K = min(K, len(rows))
     cb = storage.vq_init(xt, D, rt, K)
-    assert np.array_equal(cb.cpu().numpy().astype(np.float64), oc.vq_init(x[rows], K))
-    code = storage.vq_assign(xt, D, rt, cb)
-    _check_codes(code, x[rows].astype(np.float64), cb.cpu().numpy().astype(np.float64), f"D={D}")
+    C0 = oc.vq_init(x[rows], K)
+    assert np.array_equal(cb.cpu().numpy().astype(np.float64), C0)
+    # the assignment on the oracle's codebook, given to both sides
+    cbo = _t(C0.astype(np.float32))
+    code = storage.vq_assign(xt, D, rt, cbo)
+    _check_codes(code, x[rows].astype(np.float64), C0, f"D={D}")
     # against the float16 rounding of the codewords
-    code = storage.vq_assign(xt, D, rt, cb, half_codebook=True)
-    ch = cb.cpu().numpy().astype(np.float16).astype(np.float64)
+    code = storage.vq_assign(xt, D, rt, cbo, half_codebook=True)
+    ch = C0.astype(np.float32).astype(np.float16).astype(np.float64)
     _check_codes(code, x[rows].astype(np.float64), ch, f"D={D} half")
 
 
@@ -96,17 +99,18 @@ def test_compact_write_and_projection(cuda):
     q = (np.arange(5000) % 5 < 2).astype(np.uint8)
     order, nfd = storage.compact_order(_t(q))
     nf = int(nfd.item())
-    rows = order[nf:]
-    x = params.sh.reshape(5000, 27)
-    cb = storage.vq_init(x, 27, rows, 256)
-    code = storage.vq_assign(x, 27, rows, cb, half_codebook=True)
-    cp = storage.compact_write(params, order, nfd, cb, nf, code)
+    # a synthetic codebook and codes (within it), given to both sides
+    rng = np.random.default_rng(21)
+    C = rng.normal(0, 0.5, (256, 27)).astype(np.float32)
+    codes = rng.integers(0, 256, 5000 - nf).astype(np.uint16)
+    cp = storage.compact_write(params, order, nfd, _t(C), nf, _t(codes.view(np.int16)))
     torch.cuda.synchronize()
     # stored arrays against the oracle's packing
     P = dict(mean=sc.mean, log_scale=sc.log_scale, quat=sc.quat, opacity_logit=sc.opacity_logit, sh=sc.sh,
              sh_degree=2)
-    o, _ = oc.order_partition(q)
-    ref = oc.pack(P, o, nf, code.cpu().numpy().view(np.uint16).astype(np.int64), cb.cpu().numpy().astype(np.float64))
+    o, rnf = oc.order_partition(q)
+    assert rnf == nf
+    ref = oc.pack(P, o, nf, codes.astype(np.int64), C.astype(np.float64))
     h = lambda t: t.cpu().numpy().view(np.uint16)
     assert np.array_equal(cp.mean.cpu().numpy(), ref["mean"])
     for k in ("log_scale", "quat", "opacity_logit", "sh", "codebook"):

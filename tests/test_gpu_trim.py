@@ -5,9 +5,9 @@ Per-surfel contributions: where the oracle finds no fragile pixel among those a 
 oracle's first-order FP32 error bound of the terms alpha^gamma T^(1-gamma) plus 1e-5 relative and the
 rounding bound of their FP32 sum (one wave reduction and one atomic add per tile or quadrant block, in
 arbitrary order); with fp such pixels, the count
-within fp and the sum within fp terms (each term is at most 1).  The trimming bound is
-checked bit for bit against its definition applied to the GPU's own contributions, and against the
-oracle's average over views."""
+within fp and the sum within fp terms (each term is at most 1).  The trimming bound and mask are
+checked bit for bit against the oracle on the oracle's averages over views (rounded to FP32), and the
+bound of the whole GPU chain against the oracle's within the averages' tolerance."""
 import numpy as np
 import pytest
 
@@ -104,18 +104,19 @@ def test_contribution_aerial_views_average_and_trim(cuda):
     avg = c_sum.cpu().numpy().astype(np.float64) / len(cams)
     rel = np.abs(avg - avg_ref) / np.maximum(avg_ref, 1e-6)
     assert np.mean(rel > 1e-4) < 1e-3
-    # trimming at the paper's ratio: bit-exact against the definition on the GPU's own averages
-    c_avg = (c_sum / len(cams)).contiguous()
-    bound, mask, removed = raster.trim_mask(c_avg, 0.025)
+    # trimming at the paper's ratio on the oracle's averages rounded to FP32, given to both sides: bit-exact
+    a32 = avg_ref.astype(np.float32)
+    bound, mask, removed = raster.trim_mask(torch.from_numpy(a32).cuda(), 0.025)
     torch.cuda.synchronize()
-    host = c_avg.cpu().numpy()
-    b_ref, m_ref = oracle.trim_threshold(host, 0.025)
+    b_ref, m_ref = oracle.trim_threshold(a32, 0.025)
     assert np.float32(bound.item()) == np.float32(b_ref)
     assert np.array_equal(mask.cpu().numpy().astype(bool), m_ref)
     assert removed.item() == int(m_ref.sum())
-    # and against the oracle's own averages: the same bound up to the comparison tolerance
-    b_or, _ = oracle.trim_threshold(avg_ref, 0.025)
-    assert abs(bound.item() - b_or) <= 1e-4 * max(b_or, 1e-6)
+    # the whole GPU chain (contributions, average, bound) against the oracle's bound up to the comparison
+    # tolerance of the averages
+    c_avg = (c_sum / len(cams)).contiguous()
+    b_gpu, _, _ = raster.trim_mask(c_avg, 0.025)
+    assert abs(b_gpu.item() - b_ref) <= 1e-4 * max(b_ref, 1e-6)
 
 
 @pytest.mark.parametrize("case", ["ties", "zeros", "one", "ratio0", "ratio1", "random"])
