@@ -10,7 +10,9 @@
 //                 atomic on the tile's counter gives the entry's rank within the tile; (tile, rank,
 //                 depth bits << 32 | id) goes to the surfel's own slice, a sentinel tile to the slots of
 //                 the rect tiles it cannot reach
-//   k_tile_scan   one workgroup: exclusive prefix sum of the V * tiles counters -> ranges
+//   k_tile_scan   one workgroup: exclusive prefix sum of the V * tiles counters -> ranges; up to
+//                 kScanChunk tiles of at most kMaxViews views, k_tile_scan_order also computes the
+//                 launch order in the same workgroup (the multi-workgroup order kernels otherwise)
 //   k_place       one thread per staged slot: keys[ranges[tile] + rank] = key (no atomics)
 //   k_sort_small  one workgroup per tile: LDS bitonic sort of lists up to kSmall entries
 //   k_sort_big    lists up to kBig entries in 128 KB of LDS; longer lists are sorted in kBig chunks
@@ -43,31 +45,69 @@ __device__ __forceinline__ uint32_t rect_count(const uint16_t* r4) {
   return (tx1 - tx0) * (ty1 - ty0);
 }
 
-// block-wide exclusive scan of kScanChunk values held kScanItems per thread; returns the total
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, unsigned d) {
+  const uint32_t lo = __shfl_up((uint32_t)x, d, 64), hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)x, m, 64), hi = __shfl_xor((uint32_t)(x >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ uint64_t wave_scan(uint64_t x) {
+  const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+  for (unsigned d = 1; d < 64; d <<= 1) {
+    const uint64_t y = shfl_up64(x, d);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+constexpr int kScanWaves = kScanBlock / 64;
+
+// block-wide exclusive scan of kScanChunk values held kScanItems per thread (consecutive items per
+// thread); returns the total.  Lane scans in registers, one LDS round for the 16 wave totals; lds
+// holds at least 2 * kScanWaves entries.
 __device__ __forceinline__ uint64_t block_scan(uint64_t (&vals)[kScanItems], uint64_t* lds) {
   uint64_t s = 0;
   for (int k = 0; k < kScanItems; ++k) { const uint64_t t = vals[k]; vals[k] = s; s += t; }
-  const int t = threadIdx.x;
-  lds[t] = s;
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint64_t inc = wave_scan(s);
+  if (lane == 63u) lds[w] = inc;
   __syncthreads();
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    const uint64_t add = t >= off ? lds[t - off] : 0;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
+  if (w == 0) {
+    const uint64_t x = wave_scan(lane < (unsigned)kScanWaves ? lds[lane] : 0);
+    if (lane < (unsigned)kScanWaves) lds[kScanWaves + lane] = x;
   }
-  const uint64_t total = lds[kScanBlock - 1];
-  const uint64_t excl = lds[t] - s;
+  __syncthreads();
+  const uint64_t excl = (w > 0 ? lds[kScanWaves + w - 1] : 0) + inc - s;
+  const uint64_t total = lds[2 * kScanWaves - 1];
   for (int k = 0; k < kScanItems; ++k) vals[k] += excl;
   __syncthreads();
   return total;
+}
+
+// block-wide sum, valid in thread 0; lds holds at least kScanWaves entries (a second call right after
+// needs another lds array: thread 0 may still be reading this one)
+__device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* lds) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += shfl_xor64(x, m);
+  if ((threadIdx.x & 63u) == 0) lds[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t t = 0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < kScanWaves; ++q) t += lds[q];
+  return t;
 }
 
 // pass 2 of the surfel scan: workgroup 0 scans the chunk sums of the counts in place, workgroup 1
 // those of the visible flags (any count, kScanChunk at a time); totals[blockIdx.x] = grand total
 __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ sums0, uint64_t* __restrict__ sums1,
                                                          int64_t nb, uint64_t* __restrict__ totals) {
-  __shared__ uint64_t lds[kScanBlock];
+  __shared__ uint64_t lds[2 * kScanWaves];
   uint64_t* sums = blockIdx.x == 0 ? sums0 : sums1;
   uint64_t carry = 0;
   for (int64_t base = 0; base < nb; base += kScanChunk) {
@@ -88,7 +128,7 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __re
                                                             uint64_t* __restrict__ sums_cnt,
                                                             uint64_t* __restrict__ sums_vis,
                                                             uint32_t* __restrict__ zero, int64_t nz) {
-  __shared__ uint64_t lds[2][kScanBlock];
+  __shared__ uint64_t lds[2][kScanWaves];
   for (int64_t z = (int64_t)blockIdx.x * kScanBlock + threadIdx.x; z < nz; z += (int64_t)gridDim.x * kScanBlock)
     zero[z] = 0u;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
@@ -101,19 +141,10 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __re
       f += t != 0u;
     }
   }
-  lds[0][threadIdx.x] = c;
-  lds[1][threadIdx.x] = f;
-  __syncthreads();
-  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      lds[0][threadIdx.x] += lds[0][threadIdx.x + off];
-      lds[1][threadIdx.x] += lds[1][threadIdx.x + off];
-    }
-    __syncthreads();
-  }
+  const uint64_t sc = block_sum(c, lds[0]), sf = block_sum(f, lds[1]);
   if (threadIdx.x == 0) {
-    sums_cnt[blockIdx.x] = lds[0][0];
-    sums_vis[blockIdx.x] = lds[1][0];
+    sums_cnt[blockIdx.x] = sc;
+    sums_vis[blockIdx.x] = sf;
   }
 }
 
@@ -125,7 +156,7 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
     const uint64_t* __restrict__ sums_vis, const uint64_t* __restrict__ totals, uint32_t* __restrict__ soff,
     uint32_t* __restrict__ visible, uint32_t* __restrict__ vstart, int V, int64_t capacity,
     int32_t* __restrict__ status, int64_t* __restrict__ needed) {
-  __shared__ uint64_t lds[kScanBlock];
+  __shared__ uint64_t lds[2 * kScanWaves];
   const uint64_t carry_c = sums_cnt[blockIdx.x], carry_v = sums_vis[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
   uint64_t vc[kScanItems], vv[kScanItems];
@@ -218,7 +249,7 @@ __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect
 // One workgroup: ranges[t] = exclusive prefix sum of cnt (m tile counters), ranges[m] = total.
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const uint32_t* __restrict__ cnt, int64_t m,
                                                           uint32_t* __restrict__ ranges) {
-  __shared__ uint64_t lds[kScanBlock];
+  __shared__ uint64_t lds[2 * kScanWaves];
   uint64_t carry = 0;
   for (int64_t base = 0; base < m; base += kScanChunk) {
     const int64_t b0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -236,27 +267,22 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const uint32_t* __rest
 // scanned with its carry.
 __global__ __launch_bounds__(kScanBlock) void k_u32_sums(const uint32_t* __restrict__ a, int64_t m,
                                                          uint64_t* __restrict__ sums) {
-  __shared__ uint64_t lds[kScanBlock];
+  __shared__ uint64_t lds[2 * kScanWaves];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint64_t c = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
     if (idx < m) c += a[idx];
   }
-  lds[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = lds[0];
+  const uint64_t t = block_sum(c, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_u32_apply(const uint32_t* __restrict__ a, int64_t m,
                                                           const uint64_t* __restrict__ sums,
                                                           const uint64_t* __restrict__ total,
                                                           uint32_t* __restrict__ out) {
-  __shared__ uint64_t lds[kScanBlock];
+  __shared__ uint64_t lds[2 * kScanWaves];
   const uint64_t carry = sums[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
   uint64_t vals[kScanItems];
@@ -394,6 +420,7 @@ __global__ __launch_bounds__(1024) void k_sort_big(const uint32_t* __restrict__ 
 // heaviest tiles go first (longest-processing-time order): a stable counting sort of a view chunk's
 // tiles by a log-scale bucket of their list length, descending, tiles in index order within a bucket.
 constexpr int kOrdBuckets = 64;
+static_assert(kOrdBuckets == 64, "the order kernels keep one bucket per lane");
 constexpr int kOrdChunk = 1024;  // tiles per workgroup (16 waves)
 
 __device__ __forceinline__ int order_bucket(uint32_t len) {
@@ -402,6 +429,19 @@ __device__ __forceinline__ int order_bucket(uint32_t len) {
   const int half = e >= 1 ? (int)((len >> (e - 1)) & 1u) : 0;
   const int b = 2 * e + 1 + half;
   return b < kOrdBuckets ? b : kOrdBuckets - 1;
+}
+
+// lanes of this wave whose bucket equals the calling lane's (bk in [0, kOrdBuckets), -1 for none; the
+// result is meaningful for bk >= 0): one ballot per bit of the 6-bit bucket
+__device__ __forceinline__ unsigned long long same_bucket(int bk) {
+  unsigned long long same = __ballot(bk >= 0);
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const bool bit = bk >= 0 && ((bk >> b) & 1);
+    const unsigned long long B = __ballot(bit);
+    same &= bit ? B : ~B;
+  }
+  return same;
 }
 
 __global__ __launch_bounds__(kOrdChunk) void k_order_hist(const uint32_t* __restrict__ ranges, int64_t base, int T,
@@ -443,13 +483,12 @@ __global__ __launch_bounds__(kOrdChunk) void k_order_place(const uint32_t* __res
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * kOrdChunk + threadIdx.x;
   const int bk = t < T ? order_bucket(ranges[base + t + 1] - ranges[base + t]) : -1;
-  uint32_t rank = 0;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int k = 0; k < kOrdBuckets; ++k) {
-    const unsigned long long msk = __ballot(bk == k);
-    if (bk == k) rank = (uint32_t)__popcll(msk & lt);
-    if (lane == 0) wc[w][k] = (uint32_t)__popcll(msk);
-  }
+  const unsigned long long same = same_bucket(bk);
+  const uint32_t rank = bk >= 0 ? (uint32_t)__popcll(same & lt) : 0u;
+  wc[w][lane] = 0;  // kOrdBuckets == 64: one bucket per lane
+  // the first lane of each bucket present writes its count (after the zeroing: one wave, LDS in order)
+  if (bk >= 0 && rank == 0) wc[w][bk] = (uint32_t)__popcll(same);
   __syncthreads();
   if (threadIdx.x < kOrdBuckets) {
     uint32_t run = 0;
@@ -461,6 +500,72 @@ __global__ __launch_bounds__(kOrdChunk) void k_order_place(const uint32_t* __res
   }
   __syncthreads();
   if (bk >= 0) order[hist[(int64_t)blockIdx.x * kOrdBuckets + bk] + wc[w][bk] + rank] = (uint32_t)t;
+}
+
+// One workgroup for up to kScanChunk tiles of at most kMaxViews views (the common single-view case):
+// the tile scan of k_tile_scan and the launch order of k_order_hist / k_order_scan / k_order_place in
+// one launch, the same results.  Wave w orders the contiguous tiles [w per, (w + 1) per): LDS counts per
+// (wave, bucket), one exchange of the 16 x 64 counts into first slots, and a placing pass over 64 tiles
+// at a time with stable ranks from the lanes that share a bucket (same_bucket).
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* __restrict__ cnt, int m,
+                                                                uint32_t* __restrict__ ranges,
+                                                                uint32_t* __restrict__ order) {
+  __shared__ uint64_t lds[2 * kScanWaves];
+  __shared__ uint32_t wc[kScanWaves][kOrdBuckets];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  {
+    const int b0 = t * kScanItems;
+    uint64_t vals[kScanItems];
+    for (int k = 0; k < kScanItems; ++k) vals[k] = b0 + k < m ? cnt[b0 + k] : 0;
+    const uint64_t tot = block_scan(vals, lds);
+    for (int k = 0; k < kScanItems; ++k)
+      if (b0 + k < m) ranges[b0 + k] = (uint32_t)vals[k];
+    if (t == 0) ranges[m] = (uint32_t)tot;
+  }
+  // kScanWaves * per >= m, per a multiple of 64
+  const int per = ((m + kScanBlock - 1) / kScanBlock) * 64;
+  const int i0 = w * per, i1 = min(m, i0 + per);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  wc[w][lane] = 0;  // kOrdBuckets == 64: one bucket per lane
+  // counts per (wave, bucket): the first lane of each bucket present in 64 tiles adds their number
+  // (one wave, LDS in program order)
+  for (int c = i0; c < i1; c += 64) {
+    const int i = c + lane;
+    const int bk = i < i1 ? order_bucket(cnt[i]) : -1;
+    const unsigned long long same = same_bucket(bk);
+    if (bk >= 0 && (same & lt) == 0) wc[w][bk] += (uint32_t)__popcll(same);
+  }
+  __syncthreads();
+  if (t < kOrdBuckets) {
+    uint32_t tot = 0;
+    for (int q = 0; q < kScanWaves; ++q) tot += wc[q][t];
+    // buckets in descending order: bucket t starts after the tiles of the buckets above it
+    uint32_t x = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_down(x, d, 64);
+      if (t + d < 64) x += y;
+    }
+    uint32_t run = x - tot;
+    for (int q = 0; q < kScanWaves; ++q) {
+      const uint32_t v = wc[q][t];
+      wc[q][t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  // wc[w][k]: next slot of bucket k for this wave's tiles
+  for (int c = i0; c < i1; c += 64) {
+    const int i = c + lane;
+    const int bk = i < i1 ? order_bucket(cnt[i]) : -1;
+    const unsigned long long same = same_bucket(bk);
+    const uint32_t rank = (uint32_t)__popcll(same & lt);
+    const uint32_t first = bk >= 0 ? wc[w][bk] : 0u;
+    if (bk >= 0) order[first + rank] = (uint32_t)i;
+    // after every lane's read above
+    if (bk >= 0 && rank == 0) wc[w][bk] = first + (uint32_t)__popcll(same);
+  }
 }
 
 }  // namespace cgv2
@@ -532,7 +637,10 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(256), 0, st, b.needed, (int64_t)1, (int64_t)0);
   }
   const int64_t nbt = scan_blocks(m);
-  if (nbt <= 16) {
+  const bool fused_order = b.order && m <= kScanChunk && V <= kMaxViews;
+  if (fused_order) {
+    hipLaunchKernelGGL(k_tile_scan_order, dim3(1), dim3(kScanBlock), 0, st, cnt, (int)m, b.ranges, b.order);
+  } else if (nbt <= 16) {
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanBlock), 0, st, cnt, m, b.ranges);
   } else {
     uint64_t* ts = (uint64_t*)(w + off[8]);
@@ -545,7 +653,7 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
                      big_count, b.status);
   hipLaunchKernelGGL(k_sort_big, dim3(256), dim3(1024), 0, st, b.ranges, keys, stk, b.ids, big_list, big_count,
                      b.status);
-  if (b.order) {
+  if (b.order && !fused_order) {
     uint32_t* hist = (uint32_t*)(w + off[9]);
     for (int v0 = 0; v0 < V; v0 += kMaxViews) {
       const int T = std::min(V - v0, kMaxViews) * tiles;

@@ -159,20 +159,25 @@ def _order_bucket(length):
     return out
 
 
-def test_launch_order_heaviest_first(cuda):
+@pytest.mark.parametrize("W,H,views", [(200, 150, 3), (1600, 1066, 1), (1000, 800, 3)])
+def test_launch_order_heaviest_first(cuda, W, H, views):
     """The bins' launch order: per chunk of views, a permutation of the chunk's tiles by descending
-    length bucket, ties in index order; rendering is unchanged by it."""
+    length bucket, ties in index order; rendering is unchanged by it.  Up to 8192 tiles in all the scan
+    and the order share one workgroup (one or several 1024-tile rounds); above, the multi-workgroup form."""
     import torch
     sc = scenes.tiny_scene(5, 3000)
-    cams = [scenes.tiny_camera(200, 150, dist=d) for d in (2.5, 3.0, 3.5)]
-    eng, _, cs = gpu_forward(sc, cams, capacity=1 << 17)
+    cams = [scenes.tiny_camera(W, H, dist=d) for d in (2.5, 3.0, 3.5)[:views]]
+    eng, _, cs = gpu_forward(sc, cams, capacity=1 << 20)
     torch.cuda.synchronize()
+    assert eng.status.item() == 0
     T = eng.tiles
-    ranges = eng.ranges.cpu().numpy().view(np.uint32).astype(np.int64)[: 3 * T + 1]
-    order = eng.order.cpu().numpy().view(np.uint32).astype(np.int64)[: 3 * T]
+    m = views * T
+    ranges = eng.ranges.cpu().numpy().view(np.uint32).astype(np.int64)[: m + 1]
+    order = eng.order.cpu().numpy().view(np.uint32).astype(np.int64)[:m]
     length = ranges[1:] - ranges[:-1]
+    assert ranges[0] == 0 and np.all(length >= 0) and ranges[-1] <= int(eng.needed.item())
     bk = _order_bucket(length)
-    ref = np.lexsort((np.arange(3 * T), -bk))
+    ref = np.lexsort((np.arange(m), -bk))
     assert np.array_equal(order, ref)
     assert len(np.unique(bk)) > 3
     # the same images without the order
