@@ -159,14 +159,16 @@ def _order_bucket(length):
     return out
 
 
-@pytest.mark.parametrize("W,H,views", [(200, 150, 3), (1600, 1066, 1), (1000, 800, 3)])
+@pytest.mark.parametrize("W,H,views", [(200, 150, 3), (1600, 1066, 1), (1000, 800, 3), (96, 64, 40)])
 def test_launch_order_heaviest_first(cuda, W, H, views):
-    """The bins' launch order: per chunk of views, a permutation of the chunk's tiles by descending
-    length bucket, ties in index order; rendering is unchanged by it.  Up to 8192 tiles in all the scan
-    and the order share one workgroup (one or several 1024-tile rounds); above, the multi-workgroup form."""
+    """The bins' launch order: per chunk of up to 32 views, a permutation of the chunk's tiles (local
+    indices) by descending length bucket, ties in index order; rendering is unchanged by it.  Up to
+    8192 tiles of at most 32 views the scan and the order share one workgroup (one or several 1024-tile
+    rounds); otherwise the multi-workgroup form (above 8192 tiles, or 40 views in two chunks)."""
     import torch
     sc = scenes.tiny_scene(5, 3000)
-    cams = [scenes.tiny_camera(W, H, dist=d) for d in (2.5, 3.0, 3.5)[:views]]
+    dists = np.linspace(2.5, 3.5, views)
+    cams = [scenes.tiny_camera(W, H, dist=float(d)) for d in dists]
     eng, _, cs = gpu_forward(sc, cams, capacity=1 << 20)
     torch.cuda.synchronize()
     assert eng.status.item() == 0
@@ -177,8 +179,10 @@ def test_launch_order_heaviest_first(cuda, W, H, views):
     length = ranges[1:] - ranges[:-1]
     assert ranges[0] == 0 and np.all(length >= 0) and ranges[-1] <= int(eng.needed.item())
     bk = _order_bucket(length)
-    ref = np.lexsort((np.arange(m), -bk))
-    assert np.array_equal(order, ref)
+    for v0 in range(0, views, 32):
+        a, b = v0 * T, min(views, v0 + 32) * T
+        ref = np.lexsort((np.arange(b - a), -bk[a:b]))
+        assert np.array_equal(order[a:b], ref), v0
     assert len(np.unique(bk)) > 3
     # the same images without the order
     img = eng.rgb.clone()
@@ -318,15 +322,19 @@ def test_densify_multi_view_matches_oracle(cuda, V):
     assert np.array_equal(st.max_radius.cpu().numpy(), ost["max_radius"].astype(np.float32))
 
 
-def test_multi_view_batch_equals_single_views(cuda):
+@pytest.mark.parametrize("views,check", [(3, (0, 1, 2)), (34, (0, 31, 32, 33))])
+def test_multi_view_batch_equals_single_views(cuda, views, check):
+    # with more than 32 views the calls run in chunks of 32 and the bins hold every view at once
     import torch
     w = scenes.workload(0)
     sc = w["scene"]
-    cams = [scenes.tiny_camera(96, 80, dist=d) for d in (2.5, 3.0, 3.5)]
+    cams = [scenes.tiny_camera(96, 80, dist=float(d)) for d in np.linspace(2.5, 3.5, views)]
     for k, c in enumerate(cams):
         c.R = np.array([[np.cos(0.3 * k), 0, np.sin(0.3 * k)], [0, 1, 0], [-np.sin(0.3 * k), 0, np.cos(0.3 * k)]])
-    engb, _, _ = gpu_forward(sc, cams, capacity=1 << 17)
-    for k, c in enumerate(cams):
+    engb, _, _ = gpu_forward(sc, cams, capacity=1 << 21)
+    assert engb.status.item() == 0
+    for k in check:
+        c = cams[k]
         e1, _, _ = gpu_forward(sc, [c], capacity=1 << 17)
         a, b = fetch_img(engb, k), fetch_img(e1, 0)
         for key in ("rgb", "depth", "depth_med", "normal", "alpha", "T", "med"):
