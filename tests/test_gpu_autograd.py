@@ -2,8 +2,8 @@
 
 A 512-surfel crop of the aerial generator (the surfels nearest a ground point) in a 64x64 window:
 autograd gradients vs the oracle's analytic gradients and vs FP64 central differences (eps 1e-4) of
-the oracle's loss; an 8-view launch equals the sum of single-view launches; nothing per fragment is
-saved for the backward."""
+the oracle's loss; 8- and 34-view launches equal the sum of single-view launches; nothing per fragment
+is saved for the backward."""
 import numpy as np
 import pytest
 
@@ -96,13 +96,15 @@ def test_autograd_matches_oracle_and_fd(cuda):
             assert np.linalg.norm(fd - an) <= 2e-3 * np.linalg.norm(fd) + 1e-9, name
 
 
-def test_batched_views_equal_sum_of_single_views(cuda):
-    sc, cams = _crop_and_cams(8)
-    tg = [scenes.random_target(20 + k, 64, 64) for k in range(8)]
+@pytest.mark.parametrize("V", [8, 34])
+def test_batched_views_equal_sum_of_single_views(cuda, V):
+    # 34 views: every call runs in chunks of 32 views
+    sc, cams = _crop_and_cams(V)
+    tg = [scenes.random_target(20 + k, 64, 64) for k in range(V)]
     eng8, g8, l8 = _autograd_grads(sc, cams, tg, cuda)
     acc = [np.zeros_like(x) for x in g8]
     ltot = 0.0
-    for k in range(8):
+    for k in range(V):
         _, g1, l1 = _autograd_grads(sc, [cams[k]], [tg[k]], cuda)
         for a, b in zip(acc, g1):
             a += b
@@ -111,4 +113,4 @@ def test_batched_views_equal_sum_of_single_views(cuda):
     for name, a, b in zip(("mean", "log_scale", "quat", "opacity_logit", "sh"), g8, acc):
         grad_close(name, a, b, rel=1e-4)
     # the only state kept for the backward is the per-pixel checkpoint (12 B / pixel) + bins
-    assert eng8.T_final.element_size() * eng8.T_final.numel() == 4 * 8 * 64 * 64
+    assert eng8.T_final.element_size() * eng8.T_final.numel() == 4 * V * 64 * 64
