@@ -228,9 +228,18 @@ def test_render_bwd_matches_oracle(tiny, cuda):
     eng.forward(params, cs)
     up = _upstream(tiny)
     g = raster.Grads(params, 1)
+    # the view-space gradients are written whole (zeros outside the view's list): sentinel-filled views
+    # at odd float offsets of larger buffers, whose guard elements must stay untouched
+    n = params.n
+    bufs = [torch.full((2 * n + 8,), 7.0, device=cuda) for _ in range(2)]
+    g.g_view_total = bufs[0][1:1 + 2 * n].view(1, 2, n)
+    g.g_view_ssim = bufs[1][3:3 + 2 * n].view(1, 2, n)
     t = {k: torch.from_numpy(v).to(cuda)[None].contiguous() for k, v in up.items()}
     eng.backward(params, cs, g, **t)
     torch.cuda.synchronize()
+    b0, b1 = bufs[0].cpu().numpy(), bufs[1].cpu().numpy()
+    assert np.all(b0[:1] == 7.0) and np.all(b0[1 + 2 * n:] == 7.0)
+    assert np.all(b1[:3] == 7.0) and np.all(b1[3 + 2 * n:] == 7.0)
     ref = oracle.backward_view(tiny["sc"], tiny["cam"], tiny["po"], tiny["off"], tiny["ids"],
                                {k: v.astype(np.float64) for k, v in up.items()})
     rp = ref["params"]
