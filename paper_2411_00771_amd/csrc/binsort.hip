@@ -2,9 +2,9 @@
 //
 // Instead of a global LSD radix sort over (view | tile | depth) keys, intersections are bucketed
 // by tile directly:
-//   surfel scan   one fused three-kernel pass over every (view, surfel): the exclusive prefix sum of
-//                 its tile count (from its rect) and the compaction of the visible ones into per-view
-//                 lists, plus the capacity check
+//   surfel scan   one fused pass of three kernels (two up to kScanBlock chunks) over every (view,
+//                 surfel): the exclusive prefix sum of its tile count (from its rect) and the compaction
+//                 of the visible ones into per-view lists, plus the capacity check
 //   k_stage       groups of lanes per visible surfel: for each tile of its rect that the surfel's
 //                 alpha >= 1/255 region reaches (reach_cell over the tile's pixel samples), a returning
 //                 atomic on the tile's counter gives the entry's rank within the tile; (tile, rank,
@@ -150,14 +150,32 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __re
 
 // pass 3 of the surfel scan: soff[e] = first staged slot of (view, surfel) e, soff[m] = total;
 // visible[pos] = surfel id of every (view, surfel) with a non-empty rect in (view, id) order,
-// vstart[v] = first entry of view v, vstart[V] = total; the total is checked against the capacity
+// vstart[v] = first entry of view v, vstart[V] = total; the total is checked against the capacity.
+// local_nsb > 0 (at most kScanBlock chunks): the sums are pass 1's raw chunk sums and each workgroup
+// adds up those before it (pass 2 is skipped); 0: the sums are pass 2's scanned ones, totals its totals.
 __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
     const uint16_t* __restrict__ rect, int64_t m, int64_t n, const uint64_t* __restrict__ sums_cnt,
-    const uint64_t* __restrict__ sums_vis, const uint64_t* __restrict__ totals, uint32_t* __restrict__ soff,
-    uint32_t* __restrict__ visible, uint32_t* __restrict__ vstart, int V, int64_t capacity,
-    int32_t* __restrict__ status, int64_t* __restrict__ needed) {
+    const uint64_t* __restrict__ sums_vis, const uint64_t* __restrict__ totals, int local_nsb,
+    uint32_t* __restrict__ soff, uint32_t* __restrict__ visible, uint32_t* __restrict__ vstart, int V,
+    int64_t capacity, int32_t* __restrict__ status, int64_t* __restrict__ needed) {
   __shared__ uint64_t lds[2 * kScanWaves];
-  const uint64_t carry_c = sums_cnt[blockIdx.x], carry_v = sums_vis[blockIdx.x];
+  __shared__ uint64_t red[4][kScanWaves];
+  __shared__ uint64_t carry[4];
+  if (local_nsb > 0) {
+    const int j = threadIdx.x;
+    const uint64_t sc = j < local_nsb ? sums_cnt[j] : 0, sv = j < local_nsb ? sums_vis[j] : 0;
+    const bool before = j < (int)blockIdx.x;
+    const uint64_t c0 = block_sum(before ? sc : 0, red[0]), c1 = block_sum(before ? sv : 0, red[1]);
+    const uint64_t t0 = block_sum(sc, red[2]), t1 = block_sum(sv, red[3]);
+    if (j == 0) { carry[0] = c0; carry[1] = c1; carry[2] = t0; carry[3] = t1; }
+  } else if (threadIdx.x == 0) {
+    carry[0] = sums_cnt[blockIdx.x];
+    carry[1] = sums_vis[blockIdx.x];
+    carry[2] = totals[0];
+    carry[3] = totals[1];
+  }
+  __syncthreads();
+  const uint64_t carry_c = carry[0], carry_v = carry[1];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
   uint64_t vc[kScanItems], vv[kScanItems];
   uint32_t flag[kScanItems];
@@ -180,9 +198,9 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
     if (i == 0) vstart[e / n] = pos;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint64_t K = totals[0];
+    const uint64_t K = carry[2];
     soff[m] = (uint32_t)(K > 0xffffffffull ? 0xffffffffull : K);
-    vstart[V] = (uint32_t)totals[1];
+    vstart[V] = (uint32_t)carry[3];
     *needed = (int64_t)K;
     if ((int64_t)K > capacity) *status = 1;
   }
@@ -623,9 +641,12 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
     // overflow check; the tile counters and the big-list count are zeroed on the way
     hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis,
                        cnt, m + 1);
-    hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
+    // up to kScanBlock chunks each apply workgroup adds up the chunk sums before it itself
+    const int local_nsb = nsb <= kScanBlock ? (int)nsb : 0;
+    if (!local_nsb) hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
     hipLaunchKernelGGL(k_surfel_apply, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, n, sums_cnt,
-                       sums_vis, totals, soff, p.visible, p.visible_start, V, b.capacity, b.status, b.needed);
+                       sums_vis, totals, local_nsb, soff, p.visible, p.visible_start, V, b.capacity, b.status,
+                       b.needed);
     const unsigned blocks = (unsigned)std::min<int64_t>((n * kGroup + 255) / 256, 8192);
     hipLaunchKernelGGL(k_stage, dim3(blocks, (unsigned)V), dim3(256), 0, st, p.rect, p.rec, n, tiles_x, tiles,
                        p.visible, p.visible_start, soff, cnt, stp, stk, b.status);
