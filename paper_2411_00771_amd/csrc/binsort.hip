@@ -165,9 +165,14 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
     const int j = threadIdx.x;
     const uint64_t sc = j < local_nsb ? sums_cnt[j] : 0, sv = j < local_nsb ? sums_vis[j] : 0;
     const bool before = j < (int)blockIdx.x;
-    const uint64_t c0 = block_sum(before ? sc : 0, red[0]), c1 = block_sum(before ? sv : 0, red[1]);
-    const uint64_t t0 = block_sum(sc, red[2]), t1 = block_sum(sv, red[3]);
-    if (j == 0) { carry[0] = c0; carry[1] = c1; carry[2] = t0; carry[3] = t1; }
+    // workgroup 0 has no chunk before it and alone needs the totals
+    if (blockIdx.x == 0) {
+      const uint64_t t0 = block_sum(sc, red[2]), t1 = block_sum(sv, red[3]);
+      if (j == 0) { carry[0] = 0; carry[1] = 0; carry[2] = t0; carry[3] = t1; }
+    } else {
+      const uint64_t c0 = block_sum(before ? sc : 0, red[0]), c1 = block_sum(before ? sv : 0, red[1]);
+      if (j == 0) { carry[0] = c0; carry[1] = c1; }
+    }
   } else if (threadIdx.x == 0) {
     carry[0] = sums_cnt[blockIdx.x];
     carry[1] = sums_vis[blockIdx.x];
