@@ -183,9 +183,10 @@ def render(proj, cam, offsets, ids):
 
 
 def render_tiles(proj, cam, offsets, ids, tiles):
-    """Render only the listed tiles: returns [ntiles, 16, 16, 12] (rgb, D, Dmed, N, A, T, margin, med id)."""
+    """Render only the listed tiles: returns [ntiles, 16, 16, 13] (rgb, D, Dmed, N, A, T, margin, id of the
+    median fragment, id of the last contributor; -1 where none)."""
     tiles = np.ascontiguousarray(tiles, np.int32)
-    out = np.full((len(tiles), 16, 16, 12), np.nan)
+    out = np.full((len(tiles), 16, 16, 13), np.nan)
     counters = np.zeros(2, np.int64)
     lib().orc_render_tiles(_p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]), _p(proj["opacity"]),
                            _p(_d(cam.as_array())), _p(np.ascontiguousarray(offsets, np.int64)),
@@ -361,6 +362,34 @@ def viewspace_grad(M, dM, width, height, ndc=True):
     if ndc:
         g = g * np.array([width / 2.0, height / 2.0])
     return g
+
+
+def eval_pairs(M, opacity, xy):
+    """Ray-splat evaluation of m (surfel, sample) pairs (Sec. 3.1, Eq. 1's alpha) with the first-order
+    FP32 error bounds the decision margins use.  M [m][9], opacity [m], xy [m][2] -> dict of rho3, rho2,
+    alpha, drho3, drho2, dalpha_rel (relative), is3d, clamped."""
+    M, o, xy = _d(M).reshape(-1, 9), _d(opacity).ravel(), _d(xy).reshape(-1, 2)
+    m = M.shape[0]
+    out = np.zeros((m, 8))
+    lib().orc_eval_pairs(ctypes.c_int64(m), _p(M), _p(o), _p(xy), _p(out))
+    keys = ("rho3", "rho2", "alpha", "drho3", "drho2", "dalpha_rel")
+    res = {k: out[:, i] for i, k in enumerate(keys)}
+    res["is3d"], res["clamped"] = out[:, 6] > 0, out[:, 7] > 0
+    return res
+
+
+def blend_trace(proj, cam, ids, x, y, cap=4096):
+    """The contributing fragments of the pixel sample (x, y) over the list ids, in blend order (Eq. 1):
+    (frag [k][5] = id, alpha, T in front, relative bound of alpha, relative bound of T behind, margin)."""
+    ids = np.ascontiguousarray(ids, np.int32)
+    frag = np.zeros((cap, 5))
+    margin = np.zeros(1)
+    L = lib()
+    L.orc_blend_trace.restype = ctypes.c_int64
+    k = L.orc_blend_trace(_p(proj["M"]), _p(proj["rgb"]), _p(proj["normal"]), _p(proj["opacity"]),
+                          _p(_d(cam.as_array())), _p(ids), ctypes.c_int64(len(ids)), ctypes.c_double(x),
+                          ctypes.c_double(y), _p(frag), ctypes.c_int64(cap), _p(margin))
+    return frag[:min(k, cap)], float(margin[0])
 
 
 def sh_eval(deg, dirs):

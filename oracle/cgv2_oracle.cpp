@@ -21,6 +21,8 @@
 //   orc_ssim_loss    (1-l) L1 + l (1 - SSIM) with an 11x11 Gaussian window (Sec. 3.1) and its gradient,
 //                    once in total and once for the SSIM term alone (the DGD source of Eq. 2)
 //   orc_sh_eval      real spherical harmonics from the associated-Legendre definition
+//   orc_eval_pairs / orc_blend_trace  the per-pair evaluation and one pixel's fragments with the bounds of the
+//                    FP32 error model behind the decision margins (so that tests can check the model)
 //
 // Readings where the paper is silent are the numbered R* items of the design notes:
 // pixel centres at (i+0.5, j+0.5); sigma of the screen low-pass filter sqrt(2)/2 px;
@@ -660,7 +662,7 @@ int orc_render(int64_t n, const double* M, const double* rgb, const double* nrm,
 // are left untouched).
 int orc_render_tiles(const double* M, const double* rgb, const double* nrm, const double* opac,
                      const double* camv, const int64_t* offsets, const int32_t* ids, int64_t ntiles,
-                     const int32_t* tiles, double* out /*[ntiles][256][12]*/, int64_t* counters) {
+                     const int32_t* tiles, double* out /*[ntiles][256][13]*/, int64_t* counters) {
   const Cam cam = load_cam(camv);
   const int tx = (cam.W + kTile - 1) / kTile;
   int64_t ne = 0, nc = 0;
@@ -675,11 +677,12 @@ int orc_render_tiles(const double* M, const double* rgb, const double* nrm, cons
         PixOut po;
         blend_pixel([&](int64_t k) { return (int64_t)ids[k]; }, offsets[t], offsets[t + 1], M, rgb, nrm, opac,
                     cam, i + 0.5, j + 0.5, po);
-        double* o = out + ((s * 256) + ly * kTile + lx) * 12;
+        double* o = out + ((s * 256) + ly * kTile + lx) * 13;
         o[0] = po.C[0]; o[1] = po.C[1]; o[2] = po.C[2]; o[3] = po.D; o[4] = po.Dmed;
         o[5] = po.N[0]; o[6] = po.N[1]; o[7] = po.N[2]; o[8] = po.A; o[9] = po.T;
         o[10] = po.margin;
         o[11] = (double)(po.med >= 0 ? ids[po.med] : -1);
+        o[12] = (double)(po.last > offsets[t] ? ids[po.last - 1] : -1);
         ne += po.n_eval;
         nc += po.n_con;
       }
@@ -987,6 +990,48 @@ int orc_project_bwd(int64_t n, int deg, const double* mean, const double* log_sc
     for (int r = 0; r < 3; ++r) d_mean[r * n + i] += dmu[r];
   }
   return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// The per-pair evaluation and its FP32 error model, exposed so that a test can hold the model against
+// an emulated FP32 evaluation (the model decides which pixels count as fragile).  For m (surfel,
+// sample) pairs: M[m][9], opac[m], xy[m][2] -> out[m][8] = rho3, rho2, alpha (clamped), drho3, drho2,
+// dalpha_rel (relative), the 3D branch flag, the clamp flag.
+// ------------------------------------------------------------------------------------------
+int orc_eval_pairs(int64_t m, const double* M, const double* opac, const double* xy, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    Eval e;
+    evaluate(M + 9 * i, opac[i], xy[2 * i], xy[2 * i + 1], e);
+    double* o = out + 8 * i;
+    o[0] = e.rho3; o[1] = e.rho2; o[2] = e.alpha; o[3] = e.drho3; o[4] = e.drho2; o[5] = e.dalpha_rel;
+    o[6] = e.is3d ? 1.0 : 0.0; o[7] = e.clamped ? 1.0 : 0.0;
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// The contributing fragments of one pixel sample (x, y) over the list ids[0 .. count), in blend order:
+// frag[k][5] = surfel id, alpha, transmittance in front, relative bound of alpha, relative bound of the
+// transmittance behind it (T (1 - alpha)) under the FP32 error model.  Returns the number of fragments
+// (at most cap are written) and the pixel's smallest decision margin in *margin.
+// ------------------------------------------------------------------------------------------
+int64_t orc_blend_trace(const double* M, const double* rgb, const double* nrm, const double* opac,
+                        const double* camv, const int32_t* ids, int64_t count, double x, double y, double* frag,
+                        int64_t cap, double* margin) {
+  const Cam cam = load_cam(camv);
+  PixOut po;
+  int64_t k = 0;
+  blend_pixel([&](int64_t e) { return (int64_t)ids[e]; }, 0, count, M, rgb, nrm, opac, cam, x, y, po,
+              [&](int64_t n, double alpha, double T, double da, double dT) {
+                if (k < cap) {
+                  double* f = frag + 5 * k;
+                  f[0] = (double)n; f[1] = alpha; f[2] = T; f[3] = da; f[4] = dT;
+                }
+                ++k;
+              });
+  *margin = po.margin;
+  return k;
 }
 
 // ------------------------------------------------------------------------------------------
