@@ -15,7 +15,17 @@
  *     images.
  *   - Every call enqueues work on the given HIP stream (NULL = the null stream) and returns
  *     without synchronising.  The library never allocates device memory, never prints and
- *     never aborts.  It holds no state besides a thread-local last-HIP-error code.
+ *     never aborts.  Its only state: a thread-local last-HIP-error code and a thread-local record
+ *     of which devices are gfx950.
+ *   - Every call that launches work first checks that the calling thread's current HIP device is a
+ *     gfx950 (CGV2_EUNSUPPORTED otherwise, also when no device is present), after its argument
+ *     checks.
+ *   - Data layout.  The problem is stated per surfel and per view (Sec. 3.1): a surfel's screen
+ *     transform, colour, normal, opacity and cutoff, per-tile lists ordered by depth, per-pixel images.
+ *     The buffers below carry exactly that, arranged for the GPU rather than as separate key/value
+ *     arrays: one 96-byte record per (view, surfel) holding the projection's outputs (read whole by the
+ *     render's staging), the tile lists as sorted ids plus ranges (the sort key is rebuilt from the
+ *     record and never stored), and the per-pixel checkpoint of the reverse pass.
  *   - Return value: CGV2_OK or a negative CGV2_E* code.  On an error nothing was enqueued
  *     (CGV2_EHIP: a launch failed; cgv2_last_hip_error() gives the hipError_t).
  *   - Conditions found on the device (intersection overflow) are reported through device

@@ -15,6 +15,19 @@ int hip_status(hipError_t e) {
   return CGV2_EHIP;
 }
 
+// The library carries gfx950 code only.  A call can launch when the calling thread's current HIP device
+// is a gfx950; the answer is kept per device for the calling thread (device properties do not change).
+int device_check() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return CGV2_EUNSUPPORTED;
+  thread_local signed char known[64] = {0};
+  if (dev < 64 && known[dev]) return known[dev] > 0 ? CGV2_OK : CGV2_EUNSUPPORTED;
+  hipDeviceProp_t prop;
+  const bool ok = hipGetDeviceProperties(&prop, dev) == hipSuccess && strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  if (dev < 64) known[dev] = ok ? 1 : -1;
+  return ok ? CGV2_OK : CGV2_EUNSUPPORTED;
+}
+
 bool cams_ok(const cgv2_camera* c, int32_t V) {
   if (!c || V < 1) return false;
   for (int v = 0; v < V; ++v) {
@@ -133,6 +146,7 @@ int cgv2_project_compact(const cgv2_surfels_compact* s, const cgv2_camera* cams,
   if (s->n_full > 0 && !s->sh) return CGV2_EINVAL;
   if (s->n_full < s->n && (!s->code || !s->codebook || s->codebook_size < 1 || s->codebook_size > 65536))
     return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
     const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
     const int rc = hip_status(cgv2_launch_project_compact(*s, pack(cams, v0, cnt), *proj, (hipStream_t)stream));
@@ -143,6 +157,7 @@ int cgv2_project_compact(const cgv2_surfels_compact* s, const cgv2_camera* cams,
 
 int cgv2_project(const cgv2_surfels* s, const cgv2_camera* cams, int32_t V, cgv2_proj* proj, void* stream) {
   if (!surfels_ok(s) || !cams_ok(cams, V) || !proj_ok(proj)) return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
     const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
     const int rc = hip_status(cgv2_launch_project(*s, pack(cams, v0, cnt), *proj, (hipStream_t)stream));
@@ -165,6 +180,7 @@ int cgv2_bin_sort(const cgv2_proj* proj, const cgv2_camera* cams, int32_t V, int
   const int tx = tiles_x(cams), ty = tiles_y(cams);
   if ((int64_t)V * tx * ty >= (int64_t)0x7fffffff) return CGV2_EINVAL;
   if (ws_bytes < cgv2_bin_sort_workspace(bins->capacity, V, tx * ty, n)) return CGV2_EWORKSPACE;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_bin_sort(*proj, n, V, tx, ty, *bins, workspace, (hipStream_t)stream));
 }
 
@@ -172,6 +188,7 @@ int cgv2_render_fwd(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_cam
                     cgv2_image* img, void* stream) {
   if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !img || n < 0) return CGV2_EINVAL;
   const int tx = tiles_x(cams), ty = tiles_y(cams);
+  if (const int dv = device_check()) return dv;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
     const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
     const int rc = hip_status(cgv2_launch_render_fwd(*proj, *bins, pack(cams, v0, cnt), n, tx, ty, *img,
@@ -185,6 +202,7 @@ int cgv2_render_count(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_c
                       uint64_t* counters, void* stream) {
   if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || !counters || n < 0) return CGV2_EINVAL;
   const int tx = tiles_x(cams), ty = tiles_y(cams);
+  if (const int dv = device_check()) return dv;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
     const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
     const int rc = hip_status(cgv2_launch_render_count(*proj, *bins, pack(cams, v0, cnt), n, tx, ty,
@@ -206,6 +224,7 @@ int cgv2_loss(const float* img, const float* target, int32_t V, int32_t width, i
     return CGV2_EINVAL;
   if ((int64_t)V * 3 > 65535) return CGV2_EINVAL;
   if (ws_bytes < cgv2_loss_workspace(width, height, V)) return CGV2_EWORKSPACE;
+  if (const int dv = device_check()) return dv;
   return hip_status(
       cgv2_launch_loss(img, target, V, width, height, lambda, d_img, d_img_ssim, loss, workspace, (hipStream_t)stream));
 }
@@ -221,6 +240,7 @@ int cgv2_render_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_bin
   if (!project_args_ok(s, proj, cams, V, g) || !records_args_ok(proj, bins, cams, V, s->n, img, up))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_render_bwd_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   const int rc = bwd_records(proj, bins, cams, V, s->n, img, up, workspace, (hipStream_t)stream);
   return rc ? rc : bwd_project(s, proj, cams, V, workspace, g, (hipStream_t)stream);
 }
@@ -230,6 +250,7 @@ int cgv2_render_bwd_records(const cgv2_proj* proj, const cgv2_bins* bins, const 
                             size_t ws_bytes, void* stream) {
   if (!records_args_ok(proj, bins, cams, V, n, img, up)) return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_render_bwd_workspace(n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return bwd_records(proj, bins, cams, V, n, img, up, workspace, (hipStream_t)stream);
 }
 
@@ -237,6 +258,7 @@ int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_ca
                      const void* workspace, size_t ws_bytes, cgv2_grads* g, void* stream) {
   if (!project_args_ok(s, proj, cams, V, g)) return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_render_bwd_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return bwd_project(s, proj, cams, V, workspace, g, (hipStream_t)stream);
 }
 
@@ -255,6 +277,7 @@ int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_
   if (!st->accum_dgd || !st->accum_total || !st->max_radius || !st->denom || !st->mask || !st->counters)
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_densify_workspace(s->n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_densify(*s, *proj, *g, V, *prm, *st, workspace, (hipStream_t)stream));
 }
 
@@ -269,6 +292,7 @@ int cgv2_contribution(const cgv2_proj* proj, const cgv2_bins* bins, const cgv2_c
   if (!proj_ok(proj) || !bins_ok(bins) || !cams_ok(cams, V) || n < 0 || !(gamma >= 0.f && gamma <= 1.f))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_contribution_workspace(n, V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   if (n == 0) return CGV2_OK;
   const hipStream_t st = (hipStream_t)stream;
   const int tx = tiles_x(cams), ty = tiles_y(cams);
@@ -294,6 +318,7 @@ int cgv2_trim_mask(const float* c, int64_t n, float ratio, float* bound, uint8_t
                    void* workspace, size_t ws_bytes, void* stream) {
   if (!c || !mask || n < 1 || !(ratio >= 0.f && ratio <= 1.f) || n > 0xffffffffLL) return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_trim_workspace(n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   const uint32_t k = (uint32_t)floor((double)ratio * (double)(n - 1));
   return hip_status(cgv2_launch_trim(c, n, k, bound, mask, removed, workspace, (hipStream_t)stream));
 }
@@ -310,6 +335,7 @@ int cgv2_densify_plan(const cgv2_surfels* s, const uint8_t* mask, const uint8_t*
   if (!action_surfels_ok(s) || !prm || !counts || (s->n > 0 && (!mask || !actions || !dst))) return CGV2_EINVAL;
   if (!(prm->dense_scale >= 0.f) || !(prm->min_opacity >= 0.f && prm->min_opacity <= 1.f)) return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_densify_plan_workspace(s->n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_densify_plan(*s, mask, remove, *prm, actions, dst, counts, workspace,
                                              (hipStream_t)stream));
 }
@@ -322,6 +348,7 @@ int cgv2_densify_apply(const cgv2_surfels* s, const uint8_t* actions, const uint
   if (s->n > 0 && (!actions || !dst || !z)) return CGV2_EINVAL;
   if (out->n > 0 && (!out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->sh || !src))
     return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_densify_apply(*s, actions, dst, counts, z, *prm, *out, src, (hipStream_t)stream));
 }
 
@@ -331,6 +358,7 @@ int cgv2_densify_gather(const float* field, int64_t n, int32_t channels, int32_t
       (blocked != 0 && blocked != 1))
     return CGV2_EINVAL;
   if (n > 0 && out_n > 0 && (!field || !src || !out)) return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_densify_gather(field, n, channels, blocked, src, counts, zero_new ? 1 : 0, out, out_n,
                                                (hipStream_t)stream));
 }
@@ -346,6 +374,7 @@ int cgv2_visibility_count(const float* points, int64_t m, const cgv2_camera* cam
         !(cams[v].znear > 0.f))
       return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_visibility_workspace(V)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   const hipStream_t st = (hipStream_t)stream;
   for (int v0 = 0; v0 < V; v0 += cgv2::kMaxViews) {
     const int cnt = V - v0 < cgv2::kMaxViews ? V - v0 : cgv2::kMaxViews;
@@ -368,6 +397,7 @@ int cgv2_crop_volume(const float* points, int64_t m, const uint32_t* count, uint
       (m > 0 && (!points || !count || !keep || !ground)))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_crop_workspace(m)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_crop(points, m, count, tau, T, keep, ground, hrange, kept, workspace,
                                      (hipStream_t)stream));
 }
@@ -378,6 +408,7 @@ int cgv2_compact_order(const uint8_t* quantize, int64_t n, uint32_t* order, int6
                        size_t ws_bytes, void* stream) {
   if (n < 0 || n >= (int64_t)0xffffffff || !n_full || (n > 0 && (!quantize || !order))) return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_compact_order_workspace(n)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_compact_order(quantize, n, order, n_full, workspace, (hipStream_t)stream));
 }
 
@@ -389,6 +420,7 @@ static bool vq_dim_ok(int32_t D) {
 int cgv2_vq_init(const float* x, int32_t D, const uint32_t* rows, int64_t m, int32_t K, float* codebook,
                  void* stream) {
   if (!vq_dim_ok(D) || m < 1 || K < 1 || K > 65536 || !x || !rows || !codebook) return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_vq_init(x, D, rows, m, K, codebook, (hipStream_t)stream));
 }
 
@@ -399,6 +431,7 @@ int cgv2_vq_assign(const float* x, int32_t D, const uint32_t* rows, int64_t m, c
   if (!vq_dim_ok(D) || m < 0 || K < 1 || K > 65536 || !codebook || (m > 0 && (!x || !rows || !code)))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_vq_assign_workspace(K)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_vq_assign(x, D, rows, m, codebook, K, half_codebook ? 1 : 0, code, workspace,
                                           (hipStream_t)stream));
 }
@@ -410,6 +443,7 @@ int cgv2_vq_update(const float* x, int32_t D, const uint32_t* rows, int64_t m, c
   if (!vq_dim_ok(D) || m < 0 || K < 1 || K > 65536 || !codebook || !counts || (m > 0 && (!x || !rows || !code)))
     return CGV2_EINVAL;
   if (!workspace || ws_bytes < cgv2_vq_update_workspace(K, D)) return workspace ? CGV2_EWORKSPACE : CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_vq_update(x, D, rows, m, code, K, codebook, counts, workspace, (hipStream_t)stream));
 }
 
@@ -420,6 +454,7 @@ int cgv2_compact_write(const cgv2_surfels* s, const uint32_t* order, const int64
     return CGV2_EINVAL;
   if (s->n > 0 && (!order || !out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->sh))
     return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
   return hip_status(cgv2_launch_compact_write(*s, order, n_full, codebook, K, *out, (hipStream_t)stream));
 }
 

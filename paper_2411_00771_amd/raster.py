@@ -153,6 +153,11 @@ class Engine:
             self.ws_bwd = torch.empty(max(L.cgv2_render_bwd_workspace(n, V), 256), dtype=torch.uint8, device=device)
             self.ws_dens = torch.empty(max(L.cgv2_densify_workspace(n, V), 256), dtype=torch.uint8, device=device)
         self.pending_ssim = None
+        # bumped by every call that rewrites the records, bins, images or checkpoint (generation) and by
+        # every loss call (loss_generation): the autograd Functions check them so that a backward never
+        # reads the state of a later forward
+        self.generation = 0
+        self.loss_generation = 0
         self.set_capacity(capacity if capacity is not None else max(1 << 20, 16 * n * V))
         self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags), ptr(self.visible),
                                ptr(self.visible_start))
@@ -195,6 +200,7 @@ class Engine:
 
     def project(self, params, cams):
         """Projects a Params or a storage.CompactParams (serving storage) set."""
+        self.generation += 1
         if getattr(params, "is_compact", False):
             check(_lib.lib().cgv2_project_compact(ctypes.byref(params.struct()), cams, self.V,
                                                   ctypes.byref(self._proj), _stream()), "cgv2_project_compact")
@@ -203,10 +209,12 @@ class Engine:
                                       _stream()), "cgv2_project")
 
     def bin_sort(self, cams):
+        self.generation += 1
         check(_lib.lib().cgv2_bin_sort(ctypes.byref(self._proj), cams, self.V, self.n, ctypes.byref(self._bins),
                                        ptr(self.ws_bin), self.ws_bin.numel(), _stream()), "cgv2_bin_sort")
 
     def render(self, cams):
+        self.generation += 1
         check(_lib.lib().cgv2_render_fwd(ctypes.byref(self._proj), ctypes.byref(self._bins), cams, self.V, self.n,
                                          ctypes.byref(self._img), _stream()), "cgv2_render_fwd")
 
@@ -219,6 +227,7 @@ class Engine:
 
     def loss(self, target, lam: float = LAMBDA_SSIM, img=None):
         img = self.rgb if img is None else img
+        self.loss_generation += 1
         check(_lib.lib().cgv2_loss(ptr(img), ptr(target), self.V, self.W, self.H, lam, ptr(self.d_img),
                                    ptr(self.d_img_ssim), ptr(self.loss_val), ptr(self.ws_loss), self.ws_loss.numel(),
                                    _stream()), "cgv2_loss")
@@ -406,6 +415,11 @@ class Rasterize2DGS(torch.autograd.Function):
     Saves nothing per fragment: the backward reads the engine's bins and the per-pixel
     checkpoint (T_final, last, med) written by the forward.  Gradients go to the parameters;
     the engine's ``grads`` also receives the total and SSIM-only view-space gradients.
+
+    The outputs are the engine's own image buffers: they hold this forward's images until the engine's
+    next forward.  A backward after another forward on the same engine raises (the checkpoint and bins it
+    needs are gone), and so does a backward after an intersection overflow (the images are not valid;
+    size the engine with ``fit_capacity`` and run again).
     """
 
     @staticmethod
@@ -414,6 +428,7 @@ class Rasterize2DGS(torch.autograd.Function):
                         sh_degree)
         engine.forward(params, cams)
         ctx.engine, ctx.cams, ctx.params = engine, cams, params
+        ctx.generation = engine.generation
         # outputs the loss does not use reach the backward as None, not as zero images: the reverse
         # pass then skips the depth / normal / alpha terms entirely
         ctx.set_materialize_grads(False)
@@ -423,12 +438,21 @@ class Rasterize2DGS(torch.autograd.Function):
     def backward(ctx, d_rgb, d_depth, d_depth_med, d_normal, d_alpha):
         eng: Engine = ctx.engine
         p = ctx.params
+        if eng.generation != ctx.generation:
+            raise RuntimeError("Rasterize2DGS.backward: the engine ran another forward after this one; its bins "
+                               "and checkpoint belong to that call (use one engine per pending graph)")
+        if eng.overflowed():
+            raise RuntimeError("Rasterize2DGS.backward: the intersection capacity overflowed in the forward "
+                               f"(needed {int(eng.needed.item())}, capacity {eng.capacity}); the images are invalid")
         # fresh zeroed gradients (the ABI accumulates), handed to autograd without a copy
         g = Grads(p, eng.V)
         eng.grads = g
         c = lambda t: None if t is None else t.contiguous()
+        # the SSIM-only image gradient, when the loss on this forward's images has left one
+        pend = eng.pending_ssim
+        d_ssim = pend[1] if pend is not None and pend[0] == ctx.generation else None
         eng.backward(p, ctx.cams, g, d_rgb=c(d_rgb), d_depth=c(d_depth), d_depth_med=c(d_depth_med),
-                     d_normal=c(d_normal), d_alpha=c(d_alpha), d_rgb_ssim=eng.pending_ssim)
+                     d_normal=c(d_normal), d_alpha=c(d_alpha), d_rgb_ssim=d_ssim)
         eng.pending_ssim = None
         return g.mean, g.log_scale, g.quat, g.opacity_logit, g.sh, None, None, None
 
@@ -441,12 +465,16 @@ class L1SSIMLoss(torch.autograd.Function):
     def forward(ctx, rgb, target, engine: Engine, lam: float):
         lv = engine.loss(target.contiguous(), lam, img=rgb.contiguous())
         ctx.engine = engine
+        ctx.generation, ctx.loss_generation = engine.generation, engine.loss_generation
         return lv[:, 0].sum()
 
     @staticmethod
     def backward(ctx, g):
         eng: Engine = ctx.engine
-        eng.pending_ssim = eng.d_img_ssim * g if not isinstance(g, float) else eng.d_img_ssim
+        if eng.loss_generation != ctx.loss_generation:
+            raise RuntimeError("L1SSIMLoss.backward: the engine ran another loss after this one; its image "
+                               "gradients belong to that call")
+        eng.pending_ssim = (ctx.generation, eng.d_img_ssim * g if not isinstance(g, float) else eng.d_img_ssim)
         return eng.d_img * g, None, None, None
 
 

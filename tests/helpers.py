@@ -115,3 +115,44 @@ def compare_lists(ranges, ids, po, cam, P=None, v=0, max_excluded=None):
     if max_excluded is not None:
         assert out["surfels"] + out["fragile_pairs"] <= max_excluded, out
     return out
+
+
+def compare_sampled_tiles(eng, ref, tiles, v=0, tol=IMG_TOL, fragile=FRAGILE):
+    """Every output of view v on the tiles the oracle rendered one by one (``oracle.render_tiles``):
+    rgb, expected and median depth (relative to the tiles' depth scale), normal, alpha, T, and the ids of
+    the median fragment and the last contributor, on the pixels whose decisions are not fragile.
+    Returns (worst error per output, fragile pixels, pixels)."""
+    W, H, tx = eng.W, eng.H, eng.tiles_x
+    img = fetch_img(eng, v)
+    ranges, ids = fetch_bins(eng)
+    ranges = ranges[v * eng.tiles:(v + 1) * eng.tiles + 1]
+    ids_ext = np.append(ids, -1)
+    worst = dict(rgb=0.0, depth=0.0, depth_med=0.0, normal=0.0, alpha=0.0, T=0.0, med=0, last=0)
+    zs = max(1.0, float(np.nanmax(np.abs(ref[..., 4]))))
+    nfr, total = 0, 0
+    for s, t in enumerate(tiles):
+        oy, ox = (t // tx) * 16, (t % tx) * 16
+        h, w = min(16, H - oy), min(16, W - ox)
+        r = ref[s, :h, :w]
+        ok = r[..., 10] >= fragile
+        nfr += int((~ok).sum())
+        total += h * w
+        win = (slice(oy, oy + h), slice(ox, ox + w))
+        diff = lambda g, k: float(np.abs(g - r[..., k])[ok].max(initial=0))
+        worst["rgb"] = max(worst["rgb"], *(diff(img["rgb"][c][win], c) for c in range(3)))
+        worst["normal"] = max(worst["normal"], *(diff(img["normal"][c][win], 5 + c) for c in range(3)))
+        worst["depth"] = max(worst["depth"], diff(img["depth"][win], 3) / zs)
+        worst["depth_med"] = max(worst["depth_med"], diff(img["depth_med"][win], 4) / zs)
+        worst["alpha"] = max(worst["alpha"], diff(img["alpha"][win], 8))
+        worst["T"] = max(worst["T"], diff(img["T"][win], 9))
+        start = ranges[t]
+        med = img["med"][win]
+        med_id = np.where(med == 0xffffffff, -1, ids_ext[np.minimum(med, len(ids))])
+        last = img["last"][win]
+        last_id = np.where(last > start, ids_ext[np.minimum(np.maximum(last - 1, 0), len(ids))], -1)
+        worst["med"] += int((med_id != r[..., 11])[ok].sum())
+        worst["last"] += int((last_id != r[..., 12])[ok].sum())
+    for k in ("rgb", "depth", "depth_med", "normal", "alpha", "T"):
+        assert worst[k] <= tol, f"{k}: max err {worst[k]:.3e} > {tol}"
+    assert worst["med"] == 0 and worst["last"] == 0, worst
+    return worst, nfr, total

@@ -191,3 +191,28 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(_lib.Cgv2Error):
         _lib.lib()
+
+
+def test_no_gfx950_device_returns_eunsupported():
+    """Valid arguments with no usable gfx950 device (this host has no GPU): every compute entry point
+    returns CGV2_EUNSUPPORTED before launching anything, after its argument checks."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    L = _lib.lib()
+    cam = _lib.Camera()
+    cam.width, cam.height, cam.fx, cam.fy = 64, 48, 50.0, 50.0
+    cams = (_lib.Camera * 1)(cam)
+    s = _lib.Surfels(10, 3, *[ctypes.c_void_p(256)] * 5)
+    p = _fake_proj()
+    assert L.cgv2_project(ctypes.byref(s), cams, 1, ctypes.byref(p), None) == _lib.CGV2_EUNSUPPORTED
+    # argument errors still come first
+    assert L.cgv2_project(ctypes.byref(s), cams, 0, ctypes.byref(p), None) == _lib.CGV2_EINVAL
+    b = _lib.Bins(1024, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), ctypes.c_void_p(1024), None)
+    ws = L.cgv2_bin_sort_workspace(1024, 1, 12, 10)
+    assert L.cgv2_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b), ctypes.c_void_p(4096), ctypes.c_size_t(ws),
+                           None) == _lib.CGV2_EUNSUPPORTED
+    lw = L.cgv2_loss_workspace(64, 48, 1)
+    assert L.cgv2_loss(*[ctypes.c_void_p(256)] * 2, 1, 64, 48, ctypes.c_float(0.2), *[ctypes.c_void_p(256)] * 4,
+                       ctypes.c_size_t(lw), None) == _lib.CGV2_EUNSUPPORTED
+    assert L.cgv2_strerror(_lib.CGV2_EUNSUPPORTED) == b"unsupported device"
