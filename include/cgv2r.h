@@ -15,8 +15,8 @@
  *     images.
  *   - Every call enqueues work on the given HIP stream (NULL = the null stream) and returns
  *     without synchronising.  The library never allocates device memory, never prints and
- *     never aborts.  Its only state: a thread-local last-HIP-error code and a thread-local record
- *     of which devices are gfx950.
+ *     never aborts.  Its only state: a thread-local last-HIP-error code, a thread-local record of
+ *     which devices are gfx950, and the fixed per-GPU buffer of cgv2_densify_stats_noalloc.
  *   - Every call that launches work first checks that the calling thread's current HIP device is a
  *     gfx950 (CGV2_EUNSUPPORTED otherwise, also when no device is present), after its argument
  *     checks.
@@ -290,6 +290,19 @@ size_t cgv2_densify_workspace(int64_t n, int32_t V);
 int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* grads, int32_t V,
                        const cgv2_densify_params* prm, cgv2_densify_state* st, void* workspace, size_t ws_bytes,
                        void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): cgv2_densify_stats with its workspace taken from a fixed buffer the
+ * library holds on each GPU (CGV2_NOALLOC_SCRATCH_BYTES, reserved when the library's code is loaded on
+ * the device and held until the process ends).  Same arguments, rules and results as
+ * cgv2_densify_stats; the caller still passes every input and output.  Allocates nothing.  Every call
+ * on one GPU shares that GPU's buffer, so calls that overlap on one GPU (other streams, other threads)
+ * race: order them.  The buffer needs no clearing (each call writes what it reads).
+ * Errors: CGV2_EINVAL as cgv2_densify_stats; CGV2_EWORKSPACE when cgv2_densify_workspace(n, V) exceeds
+ * CGV2_NOALLOC_SCRATCH_BYTES (e.g. above about 40 M surfels at 8 views); CGV2_EUNSUPPORTED; CGV2_EHIP. */
+#define CGV2_NOALLOC_SCRATCH_BYTES (16u << 20)
+int cgv2_densify_stats_noalloc(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* grads, int32_t V,
+                               const cgv2_densify_params* prm, cgv2_densify_state* st, void* hip_stream);
 
 /* Counting variant of cgv2_render_fwd for work accounting: counters[3] (device, uint64, added to)
  * receive the (pixel, entry) pairs the forward evaluates, the pairs that contribute, and the pairs

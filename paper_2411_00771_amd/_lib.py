@@ -12,6 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgv2r.so")
 
 CGV2_OK, CGV2_EINVAL, CGV2_EWORKSPACE, CGV2_EUNSUPPORTED, CGV2_EHIP = 0, -1, -2, -3, -4
+NOALLOC_SCRATCH_BYTES = 16 << 20  # CGV2_NOALLOC_SCRATCH_BYTES
 TILE = 16
 REC_FLOATS = 24
 F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16, 32
@@ -19,7 +20,7 @@ F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16,
 EXPORTS = ["cgv2_project", "cgv2_project_compact", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
            "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
            "cgv2_project_bwd", "cgv2_densify_workspace",
-           "cgv2_densify_stats", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
+           "cgv2_densify_stats", "cgv2_densify_stats_noalloc", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
            "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_densify_plan_workspace", "cgv2_densify_plan",
            "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_visibility_workspace", "cgv2_visibility_count",
            "cgv2_crop_workspace", "cgv2_crop_volume", "cgv2_compact_order_workspace", "cgv2_compact_order",
@@ -133,6 +134,9 @@ def lib():
         "cgv2_densify_workspace": (sz, [i64, i32]),
         "cgv2_densify_stats": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Grads), i32,
                                               ctypes.POINTER(DensifyParams), ctypes.POINTER(DensifyState), P, sz, P]),
+        "cgv2_densify_stats_noalloc": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj),
+                                                      ctypes.POINTER(Grads), i32, ctypes.POINTER(DensifyParams),
+                                                      ctypes.POINTER(DensifyState), P]),
         "cgv2_contribution_workspace": (sz, [i64, i32]),
         "cgv2_contribution": (ctypes.c_int, [ctypes.POINTER(Proj), ctypes.POINTER(Bins), ctypes.POINTER(Camera), i32,
                                              i64, ctypes.c_float, P, P, P, P, sz, P]),

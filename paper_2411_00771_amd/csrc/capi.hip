@@ -281,6 +281,20 @@ int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_
   return hip_status(cgv2_launch_densify(*s, *proj, *g, V, *prm, *st, workspace, (hipStream_t)stream));
 }
 
+int cgv2_densify_stats_noalloc(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* g, int32_t V,
+                               const cgv2_densify_params* prm, cgv2_densify_state* st, void* stream) {
+  if (!surfels_ok(s) || !proj || !proj->flags || !proj->radius || !g || !g->g_view_total || !prm || !st ||
+      V < 1 || V > 64)
+    return CGV2_EINVAL;
+  if (!st->accum_dgd || !st->accum_total || !st->max_radius || !st->denom || !st->mask || !st->counters)
+    return CGV2_EINVAL;
+  if (cgv2_densify_workspace(s->n, V) > (size_t)CGV2_NOALLOC_SCRATCH_BYTES) return CGV2_EWORKSPACE;
+  if (const int dv = device_check()) return dv;
+  void* scratch = nullptr;
+  if (const int rc = hip_status(cgv2_densify_scratch(&scratch))) return rc;
+  return hip_status(cgv2_launch_densify(*s, *proj, *g, V, *prm, *st, scratch, (hipStream_t)stream));
+}
+
 size_t cgv2_contribution_workspace(int64_t n, int32_t V) {
   if (n < 0 || V < 1) return 0;
   return cgv2_contribution_ws_layout(n, V);

@@ -36,6 +36,9 @@ size_t cgv2_densify_ws_layout(int64_t n, int V, size_t* off);
 hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const cgv2_grads& g, int V,
                                const cgv2_densify_params& prm, const cgv2_densify_state& st, void* ws,
                                hipStream_t stream);
+// the calling thread's current device's copy of the fixed buffer of cgv2_densify_stats_noalloc
+// (CGV2_NOALLOC_SCRATCH_BYTES); its address is looked up on the first call on each device
+hipError_t cgv2_densify_scratch(void** ptr);
 
 // contribution-based trimming (render.hip: the traversal; trim.hip: the rest)
 hipError_t cgv2_launch_contribution(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,

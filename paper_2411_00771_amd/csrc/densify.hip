@@ -7,6 +7,8 @@
 //                scale_v = max(omega a_tot / a_ssim, 1) (deterministic)
 // k_densify      updates the per-surfel state and the masks; per-workgroup counter partials
 // k_count_final  one workgroup adds the partials to the counters (no same-address atomics)
+#include <atomic>
+
 #include "cgv2r_device.h"
 #include "cgv2r_kernels.h"
 
@@ -190,4 +192,31 @@ hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const 
     hipLaunchKernelGGL(cgv2::k_count_final, dim3(1), dim3(cgv2::kDBlock), 0, stream, cpart, nbd, st.counters);
   }
   return hipGetLastError();
+}
+
+// ---- fixed device buffer of cgv2_densify_stats_noalloc ------------------------------------------
+// One array per GPU, held until the process ends.  Host code never uses the array's name (on the host
+// it is a stand-in, not a device address): the first call on each device looks its address up with that
+// device current and keeps it.
+static __device__ __align__(256) unsigned char scratch[CGV2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t cgv2_densify_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
+  }
+  *ptr = p;
+  return hipSuccess;
 }

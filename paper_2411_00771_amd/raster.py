@@ -262,16 +262,24 @@ class Engine:
                                           _stream()), "cgv2_project_bwd")
 
     def densify(self, params: Params, grads: Grads, state: DensifyState, omega=0.9, eta_min=0.05,
-                grad_threshold=2e-4):
+                grad_threshold=2e-4, no_alloc: bool = False):
+        """cgv2_densify_stats; no_alloc=True calls cgv2_densify_stats_noalloc (the library's fixed per-GPU
+        buffer instead of the engine's workspace)."""
         if state.scale.numel() < self.V or state.mask.numel() < self.n:
             raise ValueError("densify state holds fewer views or surfels than the engine")
         if grads.g_view_total.shape[0] < self.V:
             raise ValueError("gradients hold fewer views than the engine")
         prm = _lib.DensifyParams(omega, eta_min, grad_threshold)
-        check(_lib.lib().cgv2_densify_stats(ctypes.byref(params.struct()), ctypes.byref(self._proj),
-                                            ctypes.byref(grads.struct()), self.V, ctypes.byref(prm),
-                                            ctypes.byref(state.struct()), ptr(self.ws_dens), self.ws_dens.numel(),
-                                            _stream()), "cgv2_densify_stats")
+        L = _lib.lib()
+        if no_alloc:
+            check(L.cgv2_densify_stats_noalloc(ctypes.byref(params.struct()), ctypes.byref(self._proj),
+                                               ctypes.byref(grads.struct()), self.V, ctypes.byref(prm),
+                                               ctypes.byref(state.struct()), _stream()), "cgv2_densify_stats_noalloc")
+            return
+        check(L.cgv2_densify_stats(ctypes.byref(params.struct()), ctypes.byref(self._proj),
+                                   ctypes.byref(grads.struct()), self.V, ctypes.byref(prm),
+                                   ctypes.byref(state.struct()), ptr(self.ws_dens), self.ws_dens.numel(),
+                                   _stream()), "cgv2_densify_stats")
 
     # ---- contribution-based trimming (Sec. 3.3) --------------------------------------------------
     def contribution(self, cams, gamma: float = 0.5, c_view=None, c_sum=None, pixels=None):
