@@ -28,12 +28,20 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed); 78.6 without packed math
 PEAK_FP32_NONPACKED = 78.6
 PEAK_HBM_GBS = 8000.0
-# algorithmic flops per pixel-entry pair (FMA = 2): forward 36 per evaluated + 26 per contributing
-# pair; reverse 42 per walked pair + 150 per contributing pair
-F_FWD_EVAL, F_FWD_CON = 36, 26
-F_BWD_WALK, F_BWD_CON = 42, 150
-# contribution pass (Eq. 3): the evaluation, then T update and alpha^gamma T^(1-gamma) per contributing pair
-F_CON_EVAL, F_CON_CON = 36, 12
+# Algorithmic flops per (pixel, list entry) pair, counted on the oracle's operation list (each add,
+# subtract, multiply, divide and exp is one flop; compares and selects none):
+#   evaluation (every pair the forward evaluates, every pair the reverse walks): the ray-splat
+#     intersection a x b (12 + 9), u, v and rho_3d (5), rho_2d (6), exp(-rho / 2) (2), o G (1) = 35;
+#   forward blend per contributing pair: T (1 - alpha) (2), w (1), colour (6), normal (6), intersection
+#     depth (4) and its sum (2) = 21;
+#   reverse per contributing pair with a colour upstream and the SSIM-only view-space gradient (the
+#     timed step's variant): T step (2), w (1), dL/dalpha (18), colour gradient (6), after-sums (6),
+#     opacity (2), dL/drho (3), dL/dp (16), dL/da, dL/db (18), rows of M (18), and for the SSIM part
+#     dL/dalpha (18), dL/drho (3), dL/dp (16), dL/da, dL/db (18), rows 1-2 of M (6) = 151;
+#   contribution pass per contributing pair: T (1 - alpha) (2), alpha^g T^(1-g) (3), sum and count (2) = 7.
+F_FWD_EVAL, F_FWD_CON = 35, 21
+F_BWD_WALK, F_BWD_CON = 35, 151
+F_CON_EVAL, F_CON_CON = 35, 7
 
 
 def log(msg):
@@ -48,26 +56,39 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(scene, cams, targets, min_seconds=10.0):
-    """The FP64 oracle, as it stands, on whole views of the same workload (steps over the cameras until
-    min_seconds have passed, at most one pass over them)."""
+def cpu_baseline(scene, cams, targets, min_seconds=10.0, one_thread=True):
+    """The FP64 oracle, as it stands, on whole views of the same workload: on all the host cores (steps
+    over the cameras until min_seconds have passed, at most one pass over them), then on one thread
+    (one view)."""
     import oracle
-    t0 = time.perf_counter()
-    k = 0
-    while k < len(cams) and (k == 0 or time.perf_counter() - t0 < min_seconds):
-        cam, target = cams[k], targets[k]
-        proj, off, ids, img = oracle.forward_view(scene, cam)
-        lo = oracle.ssim_loss(img["rgb"], target)
-        bw = oracle.backward_view(scene, cam, proj, off, ids, dict(d_rgb=lo["d_total"], d_rgb_ssim=lo["d_ssim"]))
-        st = oracle.new_densify_state(scene.n)
-        oracle.densify_stats(bw["g_total"], bw["g_ssim"], (proj["flags"] & 1) > 0, proj["radius"], scene.log_scale,
-                             st)
-        k += 1
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    return dict(value=k / dt, unit="iters/s", cores=cores, kind="oracle",
-                sample=f"{k} full 1600x1066 training steps (views) of the 1M-surfel scene (fwd+loss+bwd, both "
-                       f"view-space gradients, densify), {dt:.1f} s")
+
+    def run(views):
+        t0 = time.perf_counter()
+        k = 0
+        while k < views and (k == 0 or time.perf_counter() - t0 < min_seconds):
+            cam, target = cams[k], targets[k]
+            proj, off, ids, img = oracle.forward_view(scene, cam)
+            lo = oracle.ssim_loss(img["rgb"], target)
+            bw = oracle.backward_view(scene, cam, proj, off, ids, dict(d_rgb=lo["d_total"], d_rgb_ssim=lo["d_ssim"]))
+            st = oracle.new_densify_state(scene.n)
+            oracle.densify_stats(bw["g_total"], bw["g_ssim"], (proj["flags"] & 1) > 0, proj["radius"],
+                                 scene.log_scale, st)
+            k += 1
+        return k, time.perf_counter() - t0
+
+    cores = len(os.sched_getaffinity(0))
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", 0)) or cores)
+    k, dt = run(len(cams))
+    out = dict(value=k / dt, unit="iters/s", cores=threads, kind="oracle",
+               sample=f"{k} full 1600x1066 training steps (views) of the 1M-surfel scene (fwd+loss+bwd, both "
+                      f"view-space gradients, densify) on {threads} threads, {dt:.1f} s")
+    if one_thread:
+        oracle.set_threads(1)
+        k1, dt1 = run(1)
+        oracle.set_threads(threads)
+        out["one_thread"] = dict(value=k1 / dt1, unit="iters/s", cores=1, seconds=round(dt1, 1),
+                                 sample="1 full 1600x1066 training step (view 0) on one thread")
+    return out
 
 
 def bench_contribution(eng, params, cams, counts, gamma=0.5, ratio=0.025, reps=3):
@@ -278,8 +299,36 @@ def bench_batched(steps, warmup, n=None):
             "speedup": round(ms_p / ms_b, 3), "steps": steps}
 
 
-def bench_serving(seconds, warmup_s, slots, n=None):
-    """Serving form: Poisson requests (200/s) of mixed resolutions against 5 M resident surfels."""
+def _trace_stats(done, warmup_s):
+    """p50 / p99 latency and served Mpix/s of the requests that arrived after the warm-up window."""
+    t_first = min(r.arrival for r in done)
+    win = [r for r in done if r.arrival - t_first >= warmup_s and r.error is None]
+    lat = np.array([r.latency for r in win])
+    px = sum(r.cam.width * r.cam.height for r in win)
+    span = max(r.done_t for r in win) - min(r.arrival for r in win)
+    arr = max(r.arrival for r in win) - min(r.arrival for r in win)
+    return {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "mpix_per_s": round(px / span / 1e6, 2),
+            "offered_mpix_per_s_window": round(px / max(arr, 1e-9) / 1e6, 2),
+            "readmitted": sum(r.tries for r in done), "errors": sum(r.error is not None for r in done)}
+
+
+def _serve_trace(srv, city, rate, seconds, seed):
+    from paper_2411_00771_amd import scenes, server
+    reqs = scenes.poisson_requests(seed, rate, seconds, scenes.SERVE_RESOLUTIONS)
+    rng = np.random.default_rng(seed + 1)
+    cams = [scenes.orbit_camera(rng, city, *scenes.SERVE_RESOLUTIONS[k]) for _, k in reqs]
+    offered = sum(c.width * c.height for c in cams) / seconds / 1e6
+    done, _ = server.run_trace(srv, cams, [t for t, _ in reqs])
+    return done, offered
+
+
+def bench_serving(seconds, warmup_s, slots, n=None, slo_ms=50.0, knee_seconds=6.0, max_batch=4,
+                  rates=(200, 300, 400, 500, 600, 800, 1000, 1300)):
+    """Serving form: Poisson requests (200/s) of mixed resolutions against 5 M resident surfels, through
+    the continuous-batching server (slots, real-byte admission) and through a plain one-slot queue; then
+    the capacity: the Poisson rate raised step by step until p99 exceeds slo_ms or the served rate falls
+    below 95 % of the offered one (the knee is the last rate that met both)."""
     import torch
     from paper_2411_00771_amd import raster, scenes, server
     w = scenes.workload(3, n_override=n)
@@ -290,30 +339,127 @@ def bench_serving(seconds, warmup_s, slots, n=None):
     cams = [scenes.orbit_camera(rng, city, *scenes.SERVE_RESOLUTIONS[k]) for _, k in reqs]
     arrivals = [t for t, _ in reqs]
     out = {}
-    for name, ns in (("continuous", slots), ("plain_queue", 1)):
+    for name, ns, mb in (("continuous", slots, 1), ("continuous_batched", slots, max_batch), ("plain_queue", 1, 1)):
         srv = server.Server(params, max_slots=ns, arena_bytes=32 << 30, intersections_per_pixel=3.0,
-                            keep_results=False)
-        # warm the allocator and the kernels
+                            keep_results=False, max_batch=mb)
+        # warm the kernels
         for c in cams[:8]:
             srv.render_alone(c)
         srv.finished.clear()
         dur = seconds if name == "continuous" else min(seconds, 10.0)
         k = sum(1 for t in arrivals if t < dur)
         done, wall = server.run_trace(srv, cams[:k], arrivals[:k])
-        lat = np.array([r.latency for r in done if r.arrival - done[0].arrival >= warmup_s and r.error is None])
-        t_first = min(r.arrival for r in done)
-        win = [r for r in done if r.arrival - t_first >= warmup_s]
-        px = sum(r.cam.width * r.cam.height for r in win)
-        span = max(r.done_t for r in win) - min(r.arrival for r in win)
-        out[name] = {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "mpix_per_s": round(px / span / 1e6, 2), "slots": ns, "seconds": dur,
-                     "readmitted": sum(r.tries for r in done)}
+        out[name] = dict(_trace_stats(done, warmup_s), slots=ns, max_batch=mb, seconds=dur,
+                         launches=srv.launches, budget_gb=round(srv.arena_bytes / 2 ** 30, 1),
+                         fixed_gb=round(srv.fixed_bytes / 2 ** 30, 2))
         log(f"[bench] serving {name}: {out[name]}")
+        del srv
+        torch.cuda.empty_cache()
     offered = sum(scenes.SERVE_RESOLUTIONS[k][0] * scenes.SERVE_RESOLUTIONS[k][1] for _, k in reqs) / seconds
     out.update(workload=w["name"], surfels=sc.n, rate_per_s=200, offered_mpix_per_s=round(offered / 1e6, 1),
                warmup_s=warmup_s)
+    # capacity: the knee of the batched server
+    srv = server.Server(params, max_slots=slots, arena_bytes=32 << 30, intersections_per_pixel=3.0,
+                        keep_results=False, max_batch=max_batch)
+    for c in cams[:8]:
+        srv.render_alone(c)
+    sweep, knee = [], None
+    for rate in rates:
+        srv.finished.clear()
+        done, offered_r = _serve_trace(srv, city, rate, knee_seconds, 3100 + rate)
+        st = dict(_trace_stats(done, 1.0), rate_per_s=rate, offered_mpix_per_s=round(offered_r, 1))
+        sweep.append(st)
+        log(f"[bench] serving capacity: {st}")
+        if st["p99_ms"] > slo_ms or st["mpix_per_s"] < 0.95 * st["offered_mpix_per_s_window"]:
+            break
+        knee = st
+    out["capacity"] = {"slo_p99_ms": slo_ms, "slots": slots, "max_batch": max_batch, "seconds_per_rate": knee_seconds,
+                       "knee_rate_per_s": knee["rate_per_s"] if knee else None,
+                       "knee_mpix_per_s": knee["mpix_per_s"] if knee else None, "sweep": sweep}
+    del srv
     return out
+
+
+def bench_largest(train_steps=5, slots=4):
+    """The largest workload: 10 M surfels (log-normal scales, 10 % degenerate elongated); one 8-view
+    1600x1066 training step (forward, loss, backward, densification statistics) timed alone, the 64
+    served 3840x2160 depth/normal renders of the nadir grid through the server alone, then both at once
+    (the training step on its own stream while the server admits the renders)."""
+    import torch
+    from paper_2411_00771_amd import raster, scenes, server
+    t0 = time.time()
+    w = scenes.workload(4)
+    sc, cams, serve_cams = w["scene"], w["cameras"], w["serve_cameras"]
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    params = raster.Params.from_scene(sc, dev)
+    V = len(cams)
+    W, H = cams[0].width, cams[0].height
+    eng = raster.Engine(sc.n, W, H, V, capacity=1 << 20)
+    cs = eng.cams(cams)
+    need = eng.fit_capacity(params, cs)
+    eng.set_capacity(int(need * 1.25) + 4096)
+    tp = raster.Params.from_scene(scenes.perturbed(sc, 78), dev)
+    eng.forward(tp, cs)
+    targets = eng.rgb.clone()
+    del tp
+    grads = raster.Grads(params, V)
+    state = raster.DensifyState(sc.n, V)
+
+    def train_step():
+        grads.zero_()
+        eng.forward(params, cs)
+        eng.loss(targets)
+        eng.backward(params, cs, grads, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
+        eng.densify(params, grads, state)
+
+    train_step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(train_steps):
+        train_step()
+    e1.record()
+    torch.cuda.synchronize()
+    assert eng.status.item() == 0
+    ms_train = e0.elapsed_time(e1) / train_steps
+    srv = server.Server(params, max_slots=slots, arena_bytes=48 << 30, intersections_per_pixel=3.0,
+                        keep_results=False)
+    srv.render_alone(serve_cams[0])
+    srv.finished.clear()
+    t = time.perf_counter()
+    for c in serve_cams:
+        srv.submit(c, arrival=t)
+    srv.drain()
+    alone_wall = time.perf_counter() - t
+    alone = list(srv.finished)
+    srv.finished.clear()
+    px = sum(c.width * c.height for c in serve_cams)
+    # both: the 64 renders queued at once, the training step on its own stream while the server admits them
+    ts = torch.cuda.Stream()
+    t = time.perf_counter()
+    for c in serve_cams:
+        srv.submit(c, arrival=t)
+    srv.poll()
+    with torch.cuda.stream(ts):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(ts)
+        train_step()
+        ev1.record(ts)
+    srv.drain()
+    torch.cuda.synchronize()
+    mix_wall = time.perf_counter() - t
+    mixed = list(srv.finished)
+    lat = lambda rs, q: round(float(np.percentile([r.latency for r in rs], q)) * 1e3, 2)
+    return {"workload": w["name"], "surfels": sc.n, "generate_s": round(gen_s, 1), "train_views": V,
+            "train_step_ms": round(ms_train, 3), "train_views_per_s": round(V * 1e3 / ms_train, 1),
+            "train_mpix_per_s": round(V * W * H / (ms_train * 1e-3) / 1e6, 1), "intersections": int(need),
+            "serve_alone": {"renders": len(alone), "wall_ms": round(alone_wall * 1e3, 1),
+                            "p50_ms": lat(alone, 50), "p99_ms": lat(alone, 99),
+                            "mpix_per_s": round(px / alone_wall / 1e6, 1)},
+            "mixed": {"wall_ms": round(mix_wall * 1e3, 1), "train_step_ms": round(ev0.elapsed_time(ev1), 3),
+                      "serve_p50_ms": lat(mixed, 50), "serve_p99_ms": lat(mixed, 99),
+                      "mpix_per_s_total": round((px + V * W * H) / mix_wall / 1e6, 1)}}
 
 
 def bench_storage(seconds=10.0, warmup_s=2.0, slots=4, n=None, ratio=0.4, codebook_size=8192, iters=10):
@@ -403,6 +549,8 @@ def main():
     ap.add_argument("--no-densify-action", action="store_true")
     ap.add_argument("--no-crop", action="store_true")
     ap.add_argument("--no-storage", action="store_true")
+    ap.add_argument("--no-largest", action="store_true")
+    ap.add_argument("--no-capacity", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -453,7 +601,7 @@ def main():
     grads = raster.Grads(params, 1)
     state = raster.DensifyState(sc.n)
 
-    names = ["project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "densify"]
+    names = ["zero_grads", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "densify"]
 
     def step(k, ev=None):
         """One training step on view k; ev maps a call index i to the event recorded before call i
@@ -465,20 +613,23 @@ def main():
                 ev[i].record()
 
         mark(0)
-        eng.project(params, c)
+        # the parameter gradients accumulate (+=) over the views of a call: a step starts from zero
+        grads.zero_()
         mark(1)
-        eng.bin_sort(c)
+        eng.project(params, c)
         mark(2)
-        eng.render(c)
+        eng.bin_sort(c)
         mark(3)
-        eng.loss(targets[k % len(cams)])
+        eng.render(c)
         mark(4)
-        eng.backward_records(c, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
+        eng.loss(targets[k % len(cams)])
         mark(5)
-        eng.project_backward(params, c, grads)
+        eng.backward_records(c, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
         mark(6)
-        eng.densify(params, grads, state)
+        eng.project_backward(params, c, grads)
         mark(7)
+        eng.densify(params, grads, state)
+        mark(8)
 
     def events(idx):
         return {i: torch.cuda.Event(enable_timing=True) for i in idx}
@@ -488,7 +639,7 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps done")
     # events around the two render kernels are recorded inside the timed region (same stream)
-    live = [events((2, 3, 4, 5)) for _ in range(args.steps)]
+    live = [events((3, 4, 5, 6)) for _ in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
@@ -500,8 +651,8 @@ def main():
     if eng.status.item() != 0:
         raise RuntimeError("intersection capacity overflowed during the timed region; result invalid")
     log(f"[bench] timed {args.steps} steps: {ms:.2f} ms")
-    per_fwd = [(k % len(cams), ev[2].elapsed_time(ev[3])) for k, ev in enumerate(live)]
-    per_bwd = [(k % len(cams), ev[4].elapsed_time(ev[5])) for k, ev in enumerate(live)]
+    per_fwd = [(k % len(cams), ev[3].elapsed_time(ev[4])) for k, ev in enumerate(live)]
+    per_bwd = [(k % len(cams), ev[5].elapsed_time(ev[6])) for k, ev in enumerate(live)]
 
     # per-call split with events between all calls (separate pass)
     tot = np.zeros(len(names))
@@ -545,7 +696,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["name"], "surfels": sc.n, "width": W, "height": H, "views": len(cams),
-                   "sh_degree": sc.sh_degree, "step": "project+bin_sort+render_fwd+loss+render_bwd+project_bwd+densify"},
+                   "sh_degree": sc.sh_degree, "step": "zero_grads+project+bin_sort+render_fwd+loss+render_bwd+project_bwd+densify"},
         "mpix_per_s": round(ips * W * H / 1e6, 2),
         "split_ms": {k: round(v, 4) for k, v in split.items()},
         # one step per view of the 16, each synchronized on its own (the breakdown pass)
@@ -578,12 +729,18 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("[bench] serving form (5M surfels, Poisson 200/s, mixed resolutions)")
-        out["serving"] = bench_serving(args.serve_seconds, 2.0, args.serve_slots)
+        out["serving"] = bench_serving(args.serve_seconds, 2.0, args.serve_slots,
+                                       rates=(() if args.no_capacity else (200, 300, 400, 500, 600, 800, 1000, 1300)))
         torch.cuda.empty_cache()
     if not args.no_storage:
         log("[bench] serving storage (SH degree 2, float16 + vector quantization)")
         out["storage"] = bench_storage()
         log(f"[bench] storage: {out['storage']}")
+        torch.cuda.empty_cache()
+    if not args.no_largest:
+        log("[bench] largest: 10M surfels, 8-view training step and 64 served 4K renders")
+        out["largest"] = bench_largest()
+        log(f"[bench] largest: {out['largest']}")
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on one view (CPU)")

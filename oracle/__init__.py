@@ -392,6 +392,11 @@ def blend_trace(proj, cam, ids, x, y, cap=4096):
     return frag[:min(k, cap)], float(margin[0])
 
 
+def set_threads(t: int) -> int:
+    """Threads of the oracle's OpenMP loops (t <= 0 leaves them); returns the number in effect."""
+    return int(lib().orc_set_threads(int(t)))
+
+
 def sh_eval(deg, dirs):
     dirs = _d(dirs)
     m = dirs.shape[0]

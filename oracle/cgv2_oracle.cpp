@@ -1035,6 +1035,20 @@ int64_t orc_blend_trace(const double* M, const double* rgb, const double* nrm, c
 }
 
 // ------------------------------------------------------------------------------------------
+// Threads of the OpenMP loops (the CPU baseline times the oracle at one thread and at all cores);
+// returns the number in effect.
+// ------------------------------------------------------------------------------------------
+int orc_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+  return omp_get_max_threads();
+#else
+  (void)t;
+  return 1;
+#endif
+}
+
+// ------------------------------------------------------------------------------------------
 // SH basis values for test pins: Y[m][(deg+1)^2] at m unit directions dirs[m][3].
 // ------------------------------------------------------------------------------------------
 int orc_sh_eval(int deg, int64_t m, const double* dirs, double* Y, double* dY) {

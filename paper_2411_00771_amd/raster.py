@@ -116,7 +116,9 @@ class Engine:
     """Buffers for V views of one resolution and n surfels; each method is one C-ABI call."""
 
     def __init__(self, n: int, width: int, height: int, views: int = 1, capacity: Optional[int] = None,
-                 device="cuda", backward: bool = True):
+                 device="cuda", backward: bool = True, images: bool = True):
+        """images=False (render-only engines whose caller binds its own buffers, see bind_bins and
+        bind_images): no image, checkpoint or bin buffers are allocated; bind them before rendering."""
         L = _lib.lib()
         self.n, self.W, self.H, self.V = int(n), int(width), int(height), int(views)
         self.tiles_x = (self.W + 15) // 16
@@ -136,15 +138,19 @@ class Engine:
         self.order = torch.empty(max(V * self.tiles, 1), dtype=torch.int32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.needed = torch.zeros(1, dtype=torch.int64, device=device)
-        self.rgb = torch.empty((V, 3, H, W), device=device)
-        self.depth = torch.empty((V, H, W), device=device)
-        self.depth_med = torch.empty((V, H, W), device=device)
-        self.normal = torch.empty((V, 3, H, W), device=device)
-        self.alpha = torch.empty((V, H, W), device=device)
-        self.T_final = torch.empty((V, H, W), device=device)
-        self.last = torch.empty((V, H, W), dtype=torch.int32, device=device)
-        self.med = torch.empty((V, H, W), dtype=torch.int32, device=device)
-        self.backward_enabled = backward
+        if images:
+            self.rgb = torch.empty((V, 3, H, W), device=device)
+            self.depth = torch.empty((V, H, W), device=device)
+            self.depth_med = torch.empty((V, H, W), device=device)
+            self.normal = torch.empty((V, 3, H, W), device=device)
+            self.alpha = torch.empty((V, H, W), device=device)
+            self.T_final = torch.empty((V, H, W), device=device)
+            self.last = torch.empty((V, H, W), dtype=torch.int32, device=device)
+            self.med = torch.empty((V, H, W), dtype=torch.int32, device=device)
+        else:
+            self.rgb = self.depth = self.depth_med = self.normal = self.alpha = None
+            self.T_final = self.last = self.med = None
+        self.backward_enabled = backward and images
         if backward:
             self.d_img = torch.empty((V, 3, H, W), device=device)
             self.d_img_ssim = torch.empty((V, 3, H, W), device=device)
@@ -158,7 +164,11 @@ class Engine:
         # reads the state of a later forward
         self.generation = 0
         self.loss_generation = 0
-        self.set_capacity(capacity if capacity is not None else max(1 << 20, 16 * n * V))
+        if images:
+            self.set_capacity(capacity if capacity is not None else max(1 << 20, 16 * n * V))
+        else:
+            self.capacity, self.ids, self.ws_bin, self.qmask = 0, None, None, None
+            self._bins = _lib.Bins(0, None, ptr(self.ranges), ptr(self.status), ptr(self.needed), ptr(self.order))
         self._proj = _lib.Proj(ptr(self.rec), ptr(self.rect), ptr(self.radius), ptr(self.flags), ptr(self.visible),
                                ptr(self.visible_start))
         self._img = _lib.Image(ptr(self.rgb), ptr(self.depth), ptr(self.depth_med), ptr(self.normal),
@@ -177,6 +187,19 @@ class Engine:
                       if self.backward_enabled else None)
         if hasattr(self, "_img"):
             self._img.qmask = ptr(self.qmask)
+
+    def bind_bins(self, ids, ws, capacity: int):
+        """Use caller-owned bins (no allocation): ids (>= capacity int32 entries) and a bin_sort workspace
+        of at least cgv2_bin_sort_workspace(capacity, V, tiles, n) bytes for the calls that follow (the
+        library checks it)."""
+        assert ids.numel() >= max(capacity, 1)
+        self.capacity, self.ids, self.ws_bin = int(capacity), ids, ws
+        self._bins.capacity, self._bins.ids = self.capacity, ptr(ids)
+
+    def bind_images(self, rgb=None, depth=None, normal=None, depth_med=None, alpha=None):
+        """Render into caller-owned images ([V][c][h][w] for the call's resolution; None = not written).
+        No checkpoint is kept: the engine then renders for serving only."""
+        self._img = _lib.Image(ptr(rgb), ptr(depth), ptr(depth_med), ptr(normal), ptr(alpha), None, None, None, None)
 
     # ---- the five calls (+ loss) -------------------------------------------------------------
     def cams(self, cams: Sequence, exact: bool = True) -> ctypes.Array:

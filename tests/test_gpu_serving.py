@@ -28,19 +28,29 @@ def _eq(a, b):
     return all(np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()) for k in ("rgb", "depth", "normal"))
 
 
-def test_alone_equals_mix_and_memory_admission(city):
+@pytest.mark.parametrize("max_batch", [1, 3])
+def test_alone_equals_mix_and_memory_admission(city, max_batch):
+    """Mixed-resolution requests through 3 slots (and, with max_batch 3, same-resolution requests batched
+    into one call): every result equals the request rendered alone, the budget is never exceeded, and the
+    arena is whole again at the end."""
     from paper_2411_00771_amd import server
-    srv = server.Server(city["params"], max_slots=3, arena_bytes=64 << 20, max_width=480, max_height=270)
+    srv = server.Server(city["params"], max_slots=3, arena_bytes=(64 if max_batch == 1 else 256) << 20, max_width=480,
+                        max_height=270, max_batch=max_batch)
     mix = [srv.submit(c) for c in city["cams"]]
     peak = 0
     while srv.poll():
         peak = max(peak, srv.arena_used)
         assert srv.arena_used <= srv.arena_bytes
-        assert sum(s.req is not None for s in srv.slots) <= 3
+        assert sum(s.launch is not None for s in srv.slots) <= 3
+    srv.drain()
     assert all(r.done and r.error is None for r in mix)
-    assert peak > 0
+    assert peak > srv.fixed_bytes
+    assert srv.arena.used == 0 and srv.arena.free == [(0, srv.arena.size)]
+    if max_batch > 1:
+        assert srv.launches < len(mix)
+    ref = server.Server(city["params"], max_slots=1, arena_bytes=64 << 20, max_width=480, max_height=270)
     for r in mix:
-        alone = srv.render_alone(r.cam)
+        alone = ref.render_alone(r.cam)
         assert alone.error is None
         assert _eq(alone.result, r.result), r.rid
 
@@ -60,10 +70,15 @@ def test_overflow_is_readmitted(city):
 
 def test_oversize_request_rejected_not_stuck(city):
     from paper_2411_00771_amd import server
-    srv = server.Server(city["params"], max_slots=2, arena_bytes=1 << 20, max_width=480, max_height=270)
+    # a budget that holds the slots' fixed buffers and 1 MiB more: no 480x270 request fits
+    fixed = server.fixed_bytes(city["params"].n, max_slots=2, max_width=480, max_height=270)
+    srv = server.Server(city["params"], max_slots=2, arena_bytes=fixed + (1 << 20), max_width=480, max_height=270)
     r = srv.submit(city["cams"][2])
     srv.drain()
     assert r.done and r.error is not None
+    # a budget that cannot even hold the slots is refused at construction
+    with pytest.raises(ValueError):
+        server.Server(city["params"], max_slots=2, arena_bytes=fixed // 2, max_width=480, max_height=270)
 
 
 def test_served_render_matches_oracle(city):
