@@ -603,7 +603,16 @@ def main():
 
     names = ["zero_grads", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "densify"]
 
-    def step(k, ev=None):
+    # The parameter gradients accumulate (+=) over the views of a call, so a step starts from zeroed
+    # gradients.  In the timed loop the zeroing runs on a second stream (default priority), after the
+    # previous step's chain to the parameters and overlapped with this step's forward; the chain waits
+    # for it.  The per-call split zeroes in line.
+    zstream = torch.cuda.Stream()
+    grads_free = torch.cuda.Event()   # the previous step's parameter gradients are done
+    grads_zeroed = torch.cuda.Event()
+    grads_free.record()
+
+    def step(k, ev=None, overlap=False):
         """One training step on view k; ev maps a call index i to the event recorded before call i
         (index len(names) = after the last call)."""
         c = cams[k % len(cams)]
@@ -613,8 +622,13 @@ def main():
                 ev[i].record()
 
         mark(0)
-        # the parameter gradients accumulate (+=) over the views of a call: a step starts from zero
-        grads.zero_()
+        if overlap:
+            zstream.wait_event(grads_free)
+            with torch.cuda.stream(zstream):
+                grads.zero_()
+                grads_zeroed.record(zstream)
+        else:
+            grads.zero_()
         mark(1)
         eng.project(params, c)
         mark(2)
@@ -626,7 +640,11 @@ def main():
         mark(5)
         eng.backward_records(c, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
         mark(6)
+        if overlap:
+            torch.cuda.current_stream().wait_event(grads_zeroed)
         eng.project_backward(params, c, grads)
+        if overlap:
+            grads_free.record()
         mark(7)
         eng.densify(params, grads, state)
         mark(8)
@@ -635,7 +653,7 @@ def main():
         return {i: torch.cuda.Event(enable_timing=True) for i in idx}
 
     for k in range(args.warmup):
-        step(k)
+        step(k, overlap=True)
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps done")
     # events around the two render kernels are recorded inside the timed region (same stream)
@@ -644,7 +662,7 @@ def main():
     torch.cuda.synchronize()
     start.record()
     for k in range(args.steps):
-        step(k, live[k])
+        step(k, live[k], overlap=True)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)

@@ -528,35 +528,69 @@ __global__ __launch_bounds__(kOrdChunk) void k_order_place(const uint32_t* __res
 
 // One workgroup for up to kScanChunk tiles of at most kMaxViews views (the common single-view case):
 // the tile scan of k_tile_scan and the launch order of k_order_hist / k_order_scan / k_order_place in
-// one launch, the same results.  Wave w orders the contiguous tiles [w per, (w + 1) per): LDS counts per
-// (wave, bucket), one exchange of the 16 x 64 counts into first slots, and a placing pass over 64 tiles
-// at a time with stable ranks from the lanes that share a bucket (same_bucket).
+// one launch, the same results.  Wave w owns the contiguous tiles [w per, (w + 1) per) and loads their
+// counts once, all at the same time (lane l holds tiles w per + 64 k + l); the scan runs over those
+// registers (wave scans in k order, one LDS exchange of the 16 wave totals); the order takes LDS counts
+// per (wave, bucket), one exchange of the 16 x 64 counts into first slots, and a placing pass with
+// stable ranks from the lanes that share a bucket (same_bucket).
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+  const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+  for (unsigned d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* __restrict__ cnt, int m,
                                                                 uint32_t* __restrict__ ranges,
                                                                 uint32_t* __restrict__ order) {
-  __shared__ uint64_t lds[2 * kScanWaves];
+  __shared__ uint32_t wtot[kScanWaves];
   __shared__ uint32_t wc[kScanWaves][kOrdBuckets];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  {
-    const int b0 = t * kScanItems;
-    uint64_t vals[kScanItems];
-    for (int k = 0; k < kScanItems; ++k) vals[k] = b0 + k < m ? cnt[b0 + k] : 0;
-    const uint64_t tot = block_scan(vals, lds);
-    for (int k = 0; k < kScanItems; ++k)
-      if (b0 + k < m) ranges[b0 + k] = (uint32_t)vals[k];
-    if (t == 0) ranges[m] = (uint32_t)tot;
-  }
-  // kScanWaves * per >= m, per a multiple of 64
+  // kScanWaves * per >= m, per a multiple of 64 and at most 64 kScanItems (m <= kScanChunk)
   const int per = ((m + kScanBlock - 1) / kScanBlock) * 64;
   const int i0 = w * per, i1 = min(m, i0 + per);
+  uint32_t c[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = i0 + 64 * k + lane;
+    c[k] = 64 * k < per && i < i1 ? cnt[i] : 0u;
+  }
+  // tile scan: exclusive prefix sums within the wave's tiles, then the wave offsets
+  uint32_t ex[kScanItems];
+  uint32_t carry = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t inc = wave_scan_u32(c[k]);
+    ex[k] = carry + inc - c[k];
+    carry += __shfl(inc, 63, 64);
+  }
+  if (lane == 0) wtot[w] = carry;
   const unsigned long long lt = (1ull << lane) - 1ull;
   wc[w][lane] = 0;  // kOrdBuckets == 64: one bucket per lane
+  __syncthreads();
+  uint32_t off = 0, total = 0;
+  for (int q = 0; q < kScanWaves; ++q) {
+    const uint32_t v = wtot[q];
+    off += q < w ? v : 0u;
+    total += v;
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = i0 + 64 * k + lane;
+    if (64 * k < per && i < i1) ranges[i] = off + ex[k];
+  }
+  if (t == 0) ranges[m] = total;
   // counts per (wave, bucket): the first lane of each bucket present in 64 tiles adds their number
   // (one wave, LDS in program order)
-  for (int c = i0; c < i1; c += 64) {
-    const int i = c + lane;
-    const int bk = i < i1 ? order_bucket(cnt[i]) : -1;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (i0 + 64 * k >= i1) break;
+    const int i = i0 + 64 * k + lane;
+    const int bk = i < i1 ? order_bucket(c[k]) : -1;
     const unsigned long long same = same_bucket(bk);
     if (bk >= 0 && (same & lt) == 0) wc[w][bk] += (uint32_t)__popcll(same);
   }
@@ -580,9 +614,11 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
   }
   __syncthreads();
   // wc[w][k]: next slot of bucket k for this wave's tiles
-  for (int c = i0; c < i1; c += 64) {
-    const int i = c + lane;
-    const int bk = i < i1 ? order_bucket(cnt[i]) : -1;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (i0 + 64 * k >= i1) break;
+    const int i = i0 + 64 * k + lane;
+    const int bk = i < i1 ? order_bucket(c[k]) : -1;
     const unsigned long long same = same_bucket(bk);
     const uint32_t rank = (uint32_t)__popcll(same & lt);
     const uint32_t first = bk >= 0 ? wc[w][bk] : 0u;

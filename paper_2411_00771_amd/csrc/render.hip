@@ -114,8 +114,10 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
 
 // Per-surfel terms of a lane at its quadrant-0 pixel; pixel k sits at (xr0 + 8 (k & 1), yr0 + 8 (k >> 1))
 // relative to the projected centre.
+// (c1x, c1y, c2x, c2y, cwx, cwy) are the coefficients of x' and y' in P1, P2 and w: a pixel 8 columns or
+// rows further adds 8 times them (exact in FP32, so one FMA per term).
 struct LaneTerms {
-  float xr0, yr0, p1, p2, wb, d1x, d1y, d2x, d2y, dwx, dwy;
+  float xr0, yr0, p1, p2, wb, c1x, c1y, c2x, c2y, cwx, cwy;
 };
 
 __device__ __forceinline__ void lane_terms(float lx0, float ly0, const float4& q0, const float4& q1, const float4& q2,
@@ -125,12 +127,12 @@ __device__ __forceinline__ void lane_terms(float lx0, float ly0, const float4& q
   t.p1 = fmaf(q0.z, t.xr0, q0.w * t.yr0);
   t.p2 = fmaf(q1.x, t.xr0, q1.y * t.yr0);
   t.wb = fmaf(q1.w, t.xr0, fmaf(q2.x, t.yr0, q1.z));
-  t.d1x = 8.f * q0.z;
-  t.d1y = 8.f * q0.w;
-  t.d2x = 8.f * q1.x;
-  t.d2y = 8.f * q1.y;
-  t.dwx = 8.f * q1.w;
-  t.dwy = 8.f * q2.x;
+  t.c1x = q0.z;
+  t.c1y = q0.w;
+  t.c2x = q1.x;
+  t.c2y = q1.y;
+  t.cwx = q1.w;
+  t.cwy = q2.x;
 }
 
 // Evaluation of one staged surfel at pixel k of a lane, shared by the forward and the reverse so that
@@ -149,14 +151,14 @@ __device__ __forceinline__ void eval_px(const LaneTerms& t, float lo, Px& e) {
   e.P2 = t.p2;
   e.w = t.wb;
   if (k & 1) {
-    e.P1 += t.d1x;
-    e.P2 += t.d2x;
-    e.w += t.dwx;
+    e.P1 = fmaf(8.f, t.c1x, e.P1);
+    e.P2 = fmaf(8.f, t.c2x, e.P2);
+    e.w = fmaf(8.f, t.cwx, e.w);
   }
   if (k >> 1) {
-    e.P1 += t.d1y;
-    e.P2 += t.d2y;
-    e.w += t.dwy;
+    e.P1 = fmaf(8.f, t.c1y, e.P1);
+    e.P2 = fmaf(8.f, t.c2y, e.P2);
+    e.w = fmaf(8.f, t.cwy, e.w);
   }
   const float r2 = fmaf(e.xr, e.xr, e.yr * e.yr);
   const float nn = fmaf(e.P1, e.P1, e.P2 * e.P2);
@@ -193,8 +195,8 @@ __device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const floa
   // contribution is a zero-weight no-op for pixels that skip or stop here
   const bool take = f.T > 0.f && e.alpha >= kAlphaMin;
   if (__ballot(take) == 0) return false;
-  const float a = take ? e.alpha : 0.f;
-  const float Tn = f.T * (1.f - a);
+  // Tn is used only where the pixel takes the entry
+  const float Tn = f.T * (1.f - e.alpha);
   const bool stop = take && Tn < kTmin;
   const bool upd = take && !stop;
   n_con += upd ? 1u : 0u;
@@ -205,7 +207,7 @@ __device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const floa
     csum += upd ? c : 0.f;
     ccnt += upd ? 1.f : 0.f;
   }
-  const float wgt = upd ? a * f.T : 0.f;
+  const float wgt = upd ? e.alpha * f.T : 0.f;
   const float zf = e.is3d ? q2.w * e.iw : q2.z;
   f.C[0] = fmaf(wgt, q3.x, f.C[0]);
   f.C[1] = fmaf(wgt, q3.y, f.C[1]);
@@ -536,9 +538,9 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
     dA = fmaf(p.GA, p.Tf, dA);
   }
   // the 0.99 clamp blocks the path to o and rho; non-contributing pixels pass nothing
-  const bool live = con && !(e.araw > kAlphaMax);
-  dA = live ? dA * rom : 0.f;
-  dS = live ? dS * rom : 0.f;
+  const float rl = con && !(e.araw > kAlphaMax) ? rom : 0.f;
+  dA *= rl;
+  dS *= rl;
   acc[G_R] = fmaf(p.GC[0], wgt, acc[G_R]);
   acc[G_G] = fmaf(p.GC[1], wgt, acc[G_G]);
   acc[G_B] = fmaf(p.GC[2], wgt, acc[G_B]);
@@ -561,12 +563,15 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
   const float dr = -e.araw * dA;
   const float drs = -e.araw * dS;
   acc[G_OP] = fmaf(dA, e.araw * io, acc[G_OP]);
-  float dxr, dyr, dsx, dsy;
+  // (vx, vy) = d rho / d(x', y'): the centre gradient of either upstream is -d rho * (vx, vy)
+  float vx, vy;
   if (e.is3d) {
     const float iw = e.iw, iww = iw * iw;
     const float q1v = 2.f * e.P1 * iww, q2v = 2.f * e.P2 * iww, qw = -2.f * e.rho * iw;
     const float gP1 = dr * q1v, gP2 = dr * q2v;
-    const float gw = kGeom ? fmaf(dr, qw, -dz * zf * iw) : dr * qw;
+    // the intersection depth z_c w0 / w also depends on w
+    const float dzw = kGeom ? dz * zf * iw : 0.f;
+    const float gw = kGeom ? fmaf(dr, qw, -dzw) : dr * qw;
     acc[G_A11] = fmaf(gP1, e.xr, acc[G_A11]);
     acc[G_A12] = fmaf(gP1, e.yr, acc[G_A12]);
     acc[G_A21] = fmaf(gP2, e.xr, acc[G_A21]);
@@ -574,23 +579,22 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
     acc[G_W0] += kGeom ? fmaf(dz * zc, iw, gw) : gw;
     acc[G_W1] = fmaf(gw, e.xr, acc[G_W1]);
     acc[G_W2] = fmaf(gw, e.yr, acc[G_W2]);
-    if (kGeom) acc[G_ZC] = fmaf(dz, w0 * iw, acc[G_ZC]);
-    dxr = fmaf(gP1, a11, fmaf(gP2, a21, gw * w1));
-    dyr = fmaf(gP1, a12, fmaf(gP2, a22, gw * w2));
-    const float sP1 = drs * q1v, sP2 = drs * q2v, sw = drs * qw;
-    dsx = fmaf(sP1, a11, fmaf(sP2, a21, sw * w1));
-    dsy = fmaf(sP1, a12, fmaf(sP2, a22, sw * w2));
+    if (kGeom) {
+      acc[G_ZC] = fmaf(dz, w0 * iw, acc[G_ZC]);
+      acc[G_CX] = fmaf(dzw, w1, acc[G_CX]);
+      acc[G_CY] = fmaf(dzw, w2, acc[G_CY]);
+    }
+    vx = fmaf(q1v, a11, fmaf(q2v, a21, qw * w1));
+    vy = fmaf(q1v, a12, fmaf(q2v, a22, qw * w2));
   } else {
-    dxr = 2.f * dr * e.xr;
-    dyr = 2.f * dr * e.yr;
+    vx = 2.f * e.xr;
+    vy = 2.f * e.yr;
     if (kGeom) acc[G_ZC] += dz;
-    dsx = 2.f * drs * e.xr;
-    dsy = 2.f * drs * e.yr;
   }
-  acc[G_CX] -= dxr;
-  acc[G_CY] -= dyr;
-  acc[G_SCX] -= dsx;
-  acc[G_SCY] -= dsy;
+  acc[G_CX] = fmaf(-dr, vx, acc[G_CX]);
+  acc[G_CY] = fmaf(-dr, vy, acc[G_CY]);
+  acc[G_SCX] = fmaf(-drs, vx, acc[G_SCX]);
+  acc[G_SCY] = fmaf(-drs, vy, acc[G_SCY]);
 }
 
 // Reverse pass over one 8x8 quadrant q of a heavy tile (one pixel per lane): the whole-tile path's

@@ -431,3 +431,57 @@ def test_long_tile_lists_sorted_bit_exact(cuda):
     ranges, ids = fetch_bins(eng)
     assert (np.diff(ranges).max()) > 16384
     compare_lists(ranges, ids, oracle.project(sc, cam), cam, P=P, max_excluded=4)
+
+
+def test_tile_lists_of_every_sort_class_bit_exact(cuda):
+    """Tiles holding exactly L entries for L around every power of two of the per-tile sorts (one 256-thread
+    workgroup up to 2048 entries, one 1024-thread workgroup above), with many exact depth ties: the lists
+    equal the oracle's entry for entry."""
+    lengths = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700, 1024, 1500, 2048, 2049, 3000]
+    cam = scenes.tiny_camera(80, 64)
+    tx = (cam.width + 15) // 16
+    rng = np.random.default_rng(23)
+    f = float(np.float32(cam.fx))
+    mean, tiles_of = [], []
+    for t, L in enumerate(lengths):
+        ox, oy = (t % tx) * 16, (t // tx) * 16
+        z = np.round(rng.uniform(2.0, 4.0, L), 1)  # exact depth ties
+        px = ox + rng.uniform(5.0, 11.0, L)
+        py = oy + rng.uniform(5.0, 11.0, L)
+        mean.append(np.stack([(px - cam.cx) * z / f, (py - cam.cy) * z / f, z - 3.0]))
+        tiles_of += [t] * L
+    mean = np.concatenate(mean, 1)
+    n = mean.shape[1]
+    sc = scenes.tiny_scene(23, n)
+    sc.mean = mean.astype(np.float32)
+    sc.log_scale[:] = np.float32(np.log(0.004))
+    sc.quat[:] = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1 << 16)
+    assert eng.status.item() == 0
+    P = fetch_proj(eng)
+    ranges, ids = fetch_bins(eng)
+    assert np.array_equal(np.diff(ranges)[:len(lengths)], lengths)
+    compare_lists(ranges, ids, oracle.project(sc, cam), cam, P=P, max_excluded=0)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_property_scenes_against_oracle(cuda, seed):
+    """Seeded random small scenes of the oracle's brute-force property pin, on the GPU: 1-64 surfels of
+    scale 0.01-0.6, exact depth ties, a third edge-on, centres off screen, odd image sizes; lists bit-exact
+    and images within the tolerance on non-fragile pixels."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 65))
+    size = [(16, 16), (33, 17), (48, 40), (70, 23)][seed % 4]
+    sc = scenes.tiny_scene(seed, n)
+    sc.log_scale[:] = rng.uniform(np.log(0.01), np.log(0.6), size=sc.log_scale.shape).astype(np.float32)
+    if seed % 2:
+        sc.mean[2] = np.round(sc.mean[2], 1)
+        sc.quat[:, : n // 3] = np.array([[0.7071068], [0.7071068], [0.0], [0.0]], np.float32)
+    sc.mean[:2] *= np.float32(1.6)
+    cam = scenes.tiny_camera(*size)
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1 << 14)
+    assert eng.status.item() == 0
+    po, off, ids, io = oracle.forward_view(sc, cam)
+    ranges, gids = fetch_bins(eng)
+    compare_lists(ranges, gids, po, cam, P=fetch_proj(eng), max_excluded=4)
+    compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=0.05)
