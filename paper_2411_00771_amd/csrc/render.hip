@@ -176,11 +176,20 @@ __device__ __forceinline__ void eval_px(const LaneTerms& t, float lo, Px& e) {
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // T carries the pixel's state in its sign: T > 0 while the pixel runs (T >= 1e-4 then), -T once it has
-// stopped (or lies outside the image); the transmittance itself is |T|.
+// stopped (or lies outside the image); the transmittance itself is |T|.  'last' holds the index of the
+// last entry blended (start - 1 before the first); the image stores last + 1.
 struct FwdState {
   float T, C[3], D, Dm, N[3];
   uint32_t last, med;
 };
+
+// The entry index as a per-lane register, for the selects of 'last' and 'med' (which cannot take it from
+// a scalar register next to their lane mask).
+__device__ __forceinline__ uint32_t lane_copy(uint32_t x) {
+  uint32_t v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
+}
 
 // Returns false when no pixel of the quadrant takes the entry (wave-uniform); true otherwise, which
 // covers every entry with a contributing fragment (a superset is all the reverse pass needs).
@@ -197,8 +206,7 @@ __device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const floa
   if (__ballot(take) == 0) return false;
   // Tn is used only where the pixel takes the entry
   const float Tn = f.T * (1.f - e.alpha);
-  const bool stop = take && Tn < kTmin;
-  const bool upd = take && !stop;
+  const bool upd = take && !(Tn < kTmin);
   n_con += upd ? 1u : 0u;
   if (kContrib) {
     // log2(alpha) = min(log2(alpha_raw), log2(0.99))
@@ -219,8 +227,9 @@ __device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const floa
   const bool m = upd && f.T > 0.5f;
   f.Dm = m ? zf : f.Dm;
   f.med = m ? e_idx : f.med;
-  f.last = upd ? e_idx + 1u : f.last;
-  f.T = upd ? Tn : (stop ? -f.T : f.T);
+  f.last = upd ? e_idx : f.last;
+  // a pixel that takes the entry but would fall below 1e-4 stops in front of it
+  f.T = upd ? Tn : (take ? -f.T : f.T);
   return true;
 }
 
@@ -256,7 +265,7 @@ __device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& 
   FwdState f;
   f.T = in ? 1.f : -1.f;
   f.D = f.Dm = 0.f;
-  f.last = start;
+  f.last = start - 1u;
   f.med = 0xffffffffu;
   f.C[0] = f.C[1] = f.C[2] = 0.f;
   f.N[0] = f.N[1] = f.N[2] = 0.f;
@@ -281,7 +290,7 @@ __device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& 
         Px e;
         eval_px<q>(lt, q2.y, e);
         float csum = 0.f, ccnt = 0.f;
-        if (fwd_px<kContrib>(e, q2, q3, q4, base + (uint32_t)j, f, n_con, a.gamma, csum, ccnt)) {
+        if (fwd_px<kContrib>(e, q2, q3, q4, lane_copy(base + (uint32_t)j), f, n_con, a.gamma, csum, ccnt)) {
           if (kMask) cqq |= 1ull << j;
           if (kContrib) {
             const float ts = wave_sum_lane63(csum), tc = wave_sum_lane63(ccnt);
@@ -307,7 +316,7 @@ __device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& 
   }
   if (kContrib) return;
   if (kCount) {
-    const unsigned long long n_bwd = in ? f.last - start : 0u;
+    const unsigned long long n_bwd = in ? f.last + 1u - start : 0u;
     atomicAdd(a.counters + 0, n_eval);
     atomicAdd(a.counters + 1, n_con);
     atomicAdd(a.counters + 2, n_bwd);
@@ -335,7 +344,7 @@ __device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& 
   if (im.depth_med) im.depth_med[vp] = f.Dm;
   if (im.alpha) im.alpha[vp] = 1.f - T;
   if (im.T_final) im.T_final[vp] = T;
-  if (im.last) im.last[vp] = f.last;
+  if (im.last) im.last[vp] = f.last + 1u;
   if (im.med) im.med[vp] = f.med;
 }
 
@@ -376,7 +385,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     f[k].T = px < W && py < H ? 1.f : -1.f;
     f[k].D = 0.f;
     f[k].Dm = 0.f;
-    f[k].last = start;
+    f[k].last = start - 1u;
     f[k].med = 0xffffffffu;
     f[k].C[0] = f[k].C[1] = f[k].C[2] = 0.f;
     f[k].N[0] = f[k].N[1] = f[k].N[2] = 0.f;
@@ -402,7 +411,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
         LaneTerms lt;
         lane_terms(lx0, ly0, q0, q1, q2, lt);
-        const uint32_t e_idx = base + (uint32_t)j;
+        const uint32_t e_idx = lane_copy(base + (uint32_t)j);
         const uint64_t bit = 1ull << j;
         float csum = 0.f, ccnt = 0.f;
         bool took = false;
@@ -457,7 +466,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-      if (px < W && py < H) n_bwd += f[k].last - start;
+      if (px < W && py < H) n_bwd += f[k].last + 1u - start;
     }
     atomicAdd(a.counters + 0, n_eval);
     atomicAdd(a.counters + 1, n_con);
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     if (im.depth_med) im.depth_med[vp] = f[k].Dm;
     if (im.alpha) im.alpha[vp] = 1.f - T;
     if (im.T_final) im.T_final[vp] = T;
-    if (im.last) im.last[vp] = f[k].last;
+    if (im.last) im.last[vp] = f[k].last + 1u;
     if (im.med) im.med[vp] = f[k].med;
   }
 }
@@ -502,13 +511,53 @@ struct BwdArgs {
 
 __device__ __forceinline__ float ldg0(const float* p, int64_t i) { return p ? p[i] : 0.f; }
 
+// Per-pixel state of the reverse walk.  The upstream gradients are held multiplied by -2 (exact), which
+// makes 2 d rho come out of the chain directly (rho is half the distance, and d alpha_raw / d rho =
+// -alpha_raw); the fields that take them linearly (colour, normal, opacity) are scaled back once per
+// (surfel, tile) at the atomics.  Instead of the colour (normal, depth) sums of the fragments behind,
+// the walk keeps their dot products with the upstream gradients: sA for the total upstream, sS for the
+// SSIM-only one; the background (and the alpha-image term) starts them.
 struct BwdState {
-  float T, Tf, SC[3], SD, SN[3], GC[3], GS[3], GN[3], GD, GM, GA;
+  float T, sA, sS, GC[3], GS[3], GN[3], GD2, GD, GM;
   uint32_t last, med;
 };
 
+// Pixel (px, py) of view v: its checkpoint (T, last, median id) and upstream gradients.
+template <bool kGeom>
+__device__ __forceinline__ void bwd_init(const BwdArgs& A, const DevCam& c, int v, int px, int py, uint32_t start,
+                                         uint32_t end, BwdState& p) {
+  const int W = c.W, H = c.H;
+  const int64_t HW = (int64_t)W * H;
+  const bool in = px < W && py < H;
+  const int64_t pp = in ? (int64_t)py * W + px : 0;
+  const int64_t vp = (int64_t)v * HW + pp;
+  const int64_t v3 = (int64_t)v * 3 * HW + pp;
+  p.last = in ? min(max(A.r.img.last[vp], start), end) : start;
+  p.med = in ? A.r.img.med[vp] : 0xffffffffu;
+  const float Tf = in ? A.r.img.T_final[vp] : 1.f;
+  p.T = Tf;
+  float bA = 0.f, bS = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    p.GC[ch] = -2.f * (in ? ldg0(A.up.d_rgb, v3 + ch * HW) : 0.f);
+    p.GS[ch] = -2.f * (in ? ldg0(A.up.d_rgb_ssim, v3 + ch * HW) : 0.f);
+    p.GN[ch] = -2.f * (kGeom && in ? ldg0(A.up.d_normal, v3 + ch * HW) : 0.f);
+    bA = fmaf(p.GC[ch], c.bg[ch], bA);
+    bS = fmaf(p.GS[ch], c.bg[ch], bS);
+  }
+  p.GD = kGeom && in ? ldg0(A.up.d_depth, vp) : 0.f;
+  p.GM = kGeom && in ? ldg0(A.up.d_depth_med, vp) : 0.f;
+  p.GD2 = -2.f * p.GD;
+  // alpha = 1 - T_final: d alpha / d alpha_i = T_final / (1 - alpha_i), the same factor as the blend terms
+  const float GA = kGeom && in ? ldg0(A.up.d_alpha, vp) : 0.f;
+  p.sA = fmaf(2.f * GA, Tf, Tf * bA);
+  p.sS = Tf * bS;
+}
+
 // One pixel's share of the record gradients of a staged surfel.  Branch-free: a pixel that does not
 // take this surfel (entry at or past its 'last', or alpha below 1/255) adds zero and keeps its T.
+// acc[G_OP] collects 2 d rho (the opacity gradient is -alpha_raw d rho / o, formed at the atomics);
+// acc[G_R..G_B] and the normal sums collect -2 times their gradients.
 template <int k, bool kGeom>
 __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, const float4& q1, const float4& q2,
                                        const float4& q3, const float4& q4, uint32_t e_idx, BwdState& p,
@@ -518,64 +567,62 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
   const bool con = e_idx < p.last && e.alpha >= kAlphaMin;
   // for a quadrant without a contributing pixel every update below is the identity
   if (__ballot(con) == 0) return;
-  any = any || con;
+  any = true;  // wave-uniform: some pixel takes the entry
   const float a11 = q0.z, a12 = q0.w, a21 = q1.x, a22 = q1.y, w0 = q1.z, w1 = q1.w, w2 = q2.x;
-  const float zc = q2.z, zw = q2.w, io = q4.w;
+  const float zc = q2.z, zw = q2.w;
   const float al = con ? e.alpha : 0.f;
   const float rom = __builtin_amdgcn_rcpf(1.f - al);
   const float Tn = p.T;       // transmittance after this fragment
   const float Ti = Tn * rom;  // ... and before it
   const float wgt = al * Ti;
-  const float zf = e.is3d ? zw * e.iw : zc;
-  const float dcr = Tn * q3.x - p.SC[0], dcg = Tn * q3.y - p.SC[1], dcb = Tn * q3.z - p.SC[2];
-  float dA = fmaf(p.GC[0], dcr, fmaf(p.GC[1], dcg, p.GC[2] * dcb));
-  float dS = fmaf(p.GS[0], dcr, fmaf(p.GS[1], dcg, p.GS[2] * dcb));
+  // upstream . (this fragment's attributes), for the total and the SSIM-only upstream
+  float g = fmaf(p.GC[0], q3.x, fmaf(p.GC[1], q3.y, p.GC[2] * q3.z));
+  const float gs = fmaf(p.GS[0], q3.x, fmaf(p.GS[1], q3.y, p.GS[2] * q3.z));
+  float zf = 0.f;
   if (kGeom) {
-    dA = fmaf(p.GN[0], Tn * q4.x - p.SN[0], dA);
-    dA = fmaf(p.GN[1], Tn * q4.y - p.SN[1], dA);
-    dA = fmaf(p.GN[2], Tn * q4.z - p.SN[2], dA);
-    dA = fmaf(p.GD, Tn * zf - p.SD, dA);
-    dA = fmaf(p.GA, p.Tf, dA);
+    zf = e.is3d ? zw * e.iw : zc;
+    g = fmaf(p.GN[0], q4.x, g);
+    g = fmaf(p.GN[1], q4.y, g);
+    g = fmaf(p.GN[2], q4.z, g);
+    g = fmaf(p.GD2, zf, g);
   }
-  // the 0.99 clamp blocks the path to o and rho; non-contributing pixels pass nothing
-  const float rl = con && !(e.araw > kAlphaMax) ? rom : 0.f;
-  dA *= rl;
-  dS *= rl;
+  // 2 (1 - alpha) dL/dalpha: what lies behind minus T in front times this fragment's attributes
+  const float nA = fmaf(-Tn, g, p.sA);
+  const float nS = fmaf(-Tn, gs, p.sS);
+  p.sA = fmaf(wgt, g, p.sA);
+  p.sS = fmaf(wgt, gs, p.sS);
+  // d alpha / d alpha_raw / (1 - alpha): the 0.99 clamp blocks the path to o and rho; below it alpha is
+  // alpha_raw, and a pixel that does not take the entry has al = 0
+  const float rA = e.araw > kAlphaMax ? 0.f : al * rom;
   acc[G_R] = fmaf(p.GC[0], wgt, acc[G_R]);
   acc[G_G] = fmaf(p.GC[1], wgt, acc[G_G]);
   acc[G_B] = fmaf(p.GC[2], wgt, acc[G_B]);
-  p.SC[0] = fmaf(wgt, q3.x, p.SC[0]);
-  p.SC[1] = fmaf(wgt, q3.y, p.SC[1]);
-  p.SC[2] = fmaf(wgt, q3.z, p.SC[2]);
   float dz = 0.f;
   if (kGeom) {
     acc[G_NX] = fmaf(p.GN[0], wgt, acc[G_NX]);
     acc[G_NY] = fmaf(p.GN[1], wgt, acc[G_NY]);
     acc[G_NZ] = fmaf(p.GN[2], wgt, acc[G_NZ]);
     dz = fmaf(p.GD, wgt, con && e_idx == p.med ? p.GM : 0.f);
-    p.SN[0] = fmaf(wgt, q4.x, p.SN[0]);
-    p.SN[1] = fmaf(wgt, q4.y, p.SN[1]);
-    p.SN[2] = fmaf(wgt, q4.z, p.SN[2]);
-    p.SD = fmaf(wgt, zf, p.SD);
   }
   p.T = Ti;
-  // alpha_raw = o exp(-rho): d alpha_raw / d rho = -alpha_raw
-  const float dr = -e.araw * dA;
-  const float drs = -e.araw * dS;
-  acc[G_OP] = fmaf(dA, e.araw * io, acc[G_OP]);
-  // (vx, vy) = d rho / d(x', y'): the centre gradient of either upstream is -d rho * (vx, vy)
+  // -2 d rho of either upstream
+  const float ndr = rA * nA;
+  const float nds = rA * nS;
+  acc[G_OP] -= ndr;
+  // (vx, vy) = d rho / d(x', y') / 2: the centre gradient of either upstream is -2 d rho * (vx, vy)
   float vx, vy;
   if (e.is3d) {
+    // rho = |P|^2 / (2 w^2) with P = (P1, P2), so d rho = (P . dP) / w^2 - 2 rho dw / w
     const float iw = e.iw, iww = iw * iw;
-    const float q1v = 2.f * e.P1 * iww, q2v = 2.f * e.P2 * iww, qw = -2.f * e.rho * iw;
-    const float gP1 = dr * q1v, gP2 = dr * q2v;
+    const float u1 = e.P1 * iww, u2 = e.P2 * iww, uw = e.rho * iw;
+    const float nP1 = ndr * u1, nP2 = ndr * u2;
     // the intersection depth z_c w0 / w also depends on w
     const float dzw = kGeom ? dz * zf * iw : 0.f;
-    const float gw = kGeom ? fmaf(dr, qw, -dzw) : dr * qw;
-    acc[G_A11] = fmaf(gP1, e.xr, acc[G_A11]);
-    acc[G_A12] = fmaf(gP1, e.yr, acc[G_A12]);
-    acc[G_A21] = fmaf(gP2, e.xr, acc[G_A21]);
-    acc[G_A22] = fmaf(gP2, e.yr, acc[G_A22]);
+    const float gw = kGeom ? fmaf(ndr, uw, -dzw) : ndr * uw;
+    acc[G_A11] = fmaf(-nP1, e.xr, acc[G_A11]);
+    acc[G_A12] = fmaf(-nP1, e.yr, acc[G_A12]);
+    acc[G_A21] = fmaf(-nP2, e.xr, acc[G_A21]);
+    acc[G_A22] = fmaf(-nP2, e.yr, acc[G_A22]);
     acc[G_W0] += kGeom ? fmaf(dz * zc, iw, gw) : gw;
     acc[G_W1] = fmaf(gw, e.xr, acc[G_W1]);
     acc[G_W2] = fmaf(gw, e.yr, acc[G_W2]);
@@ -584,17 +631,48 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
       acc[G_CX] = fmaf(dzw, w1, acc[G_CX]);
       acc[G_CY] = fmaf(dzw, w2, acc[G_CY]);
     }
-    vx = fmaf(q1v, a11, fmaf(q2v, a21, qw * w1));
-    vy = fmaf(q1v, a12, fmaf(q2v, a22, qw * w2));
+    vx = fmaf(u1, a11, fmaf(u2, a21, -uw * w1));
+    vy = fmaf(u1, a12, fmaf(u2, a22, -uw * w2));
   } else {
-    vx = 2.f * e.xr;
-    vy = 2.f * e.yr;
+    vx = e.xr;
+    vy = e.yr;
     if (kGeom) acc[G_ZC] += dz;
   }
-  acc[G_CX] = fmaf(-dr, vx, acc[G_CX]);
-  acc[G_CY] = fmaf(-dr, vy, acc[G_CY]);
-  acc[G_SCX] = fmaf(-drs, vx, acc[G_SCX]);
-  acc[G_SCY] = fmaf(-drs, vy, acc[G_SCY]);
+  acc[G_CX] = fmaf(ndr, vx, acc[G_CX]);
+  acc[G_CY] = fmaf(ndr, vy, acc[G_CY]);
+  acc[G_SCX] = fmaf(nds, vx, acc[G_SCX]);
+  acc[G_SCY] = fmaf(nds, vy, acc[G_SCY]);
+}
+
+// Factor that turns the reduced value of field 'slot' into its record gradient: the staged numerator
+// coefficients carry 1/sqrt(2), the colour fields -2.  (The opacity field, 2 d rho, takes -1 / (2 o) of
+// its surfel instead.)
+__device__ __forceinline__ float slot_scale(int slot) {
+  if (slot >= G_A11 && slot <= G_A22) return kInvSqrt2;
+  return slot >= G_R && slot <= G_B ? -0.5f : 1.f;
+}
+
+// Adds one staged entry's wave-summed record gradients (acc of every lane) into (view, surfel) 'id':
+// fields G_CX..G_ZC by reduce-scatter (one atomic instruction, one lane per field), the normals (kGeom)
+// from lane 63.  sc = slot_scale of the lane's field.
+template <bool kGeom>
+__device__ __forceinline__ void bwd_commit(float (&acc)[kGradFields], int lane, int slot, float sc, float io,
+                                           float* rgv, float* rgn, uint32_t id) {
+  float red[16];
+#pragma unroll
+  for (int f = 0; f < 16; ++f) red[f] = acc[f];
+  const float tot = reduce16_scatter(red);
+  if ((lane & 12) == 0 && (kGeom || slot != G_ZC))
+    atomicAdd(rgv + (int64_t)id * kGradRow + slot, tot * (slot == G_OP ? -0.5f * io : sc));
+  if (kGeom) {
+    const float nx = wave_sum_lane63(acc[G_NX]), ny = wave_sum_lane63(acc[G_NY]), nz = wave_sum_lane63(acc[G_NZ]);
+    if (lane == 63) {
+      float* w = rgn + (int64_t)id * kGradNrm;
+      atomicAdd(w, -0.5f * nx);
+      atomicAdd(w + 1, -0.5f * ny);
+      atomicAdd(w + 2, -0.5f * nz);
+    }
+  }
 }
 
 // Reverse pass over one 8x8 quadrant q of a heavy tile (one pixel per lane): the whole-tile path's
@@ -607,42 +685,20 @@ __device__ __forceinline__ void render_bwd_quadrant(const BwdArgs& A, Stage& s, 
   const int t = (int)(b % (uint32_t)a.tiles);
   const int tx = t % a.tiles_x, ty = t / a.tiles_x;
   const DevCam& c = a.cams.c[lv];
-  const int W = c.W, H = c.H;
   const int lane = threadIdx.x;
   const int ox = tx * kTile, oy = ty * kTile;
   const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
   const int64_t vn = (int64_t)v * a.n;
-  const int64_t HW = (int64_t)W * H;
   float* rgv = A.rg.row + (int64_t)v * a.n * kGradRow;
   float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
   BwdState p;
-  {
-    const int px = ox + (lane & 7) + 8 * (q & 1), py = oy + (lane >> 3) + 8 * (q >> 1);
-    const bool in = px < W && py < H;
-    const int64_t pp = in ? (int64_t)py * W + px : 0;
-    const int64_t vp = (int64_t)v * HW + pp;
-    const int64_t v3 = (int64_t)v * 3 * HW + pp;
-    p.last = in ? min(max(a.img.last[vp], start), end) : start;
-    p.med = in ? a.img.med[vp] : 0xffffffffu;
-    p.Tf = in ? a.img.T_final[vp] : 1.f;
-    p.T = p.Tf;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      p.GC[ch] = in ? ldg0(A.up.d_rgb, v3 + ch * HW) : 0.f;
-      p.GS[ch] = in ? ldg0(A.up.d_rgb_ssim, v3 + ch * HW) : 0.f;
-      p.GN[ch] = kGeom && in ? ldg0(A.up.d_normal, v3 + ch * HW) : 0.f;
-      p.SC[ch] = p.Tf * c.bg[ch];
-      p.SN[ch] = 0.f;
-    }
-    p.GD = kGeom && in ? ldg0(A.up.d_depth, vp) : 0.f;
-    p.GM = kGeom && in ? ldg0(A.up.d_depth_med, vp) : 0.f;
-    p.GA = kGeom && in ? ldg0(A.up.d_alpha, vp) : 0.f;
-    p.SD = 0.f;
-  }
+  bwd_init<kGeom>(A, c, v, ox + (lane & 7) + 8 * (q & 1), oy + (lane >> 3) + 8 * (q >> 1), start, end, p);
   uint32_t h = p.last;
   for (int off = 1; off < 64; off <<= 1) h = max(h, __shfl_xor(h, off));
   const uint32_t hi = uniform(h);
   const float lx0 = (float)(lane & 7) + 0.5f, ly0 = (float)(lane >> 3) + 0.5f;
+  const int slot = reduce16_index(lane);
+  const float sc = slot_scale(slot);
   for (uint32_t top = hi; top > start;) {
     const uint32_t lo = top - start > 64u ? top - 64u : start;
     const uint32_t idx = lo + lane;
@@ -659,27 +715,8 @@ __device__ __forceinline__ void render_bwd_quadrant(const BwdArgs& A, Stage& s, 
       for (int f = 0; f < kGradFields; ++f) acc[f] = 0.f;
       bool any = false;
       bwd_px<q, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p, acc, any);
-      if (__ballot(any) == 0) continue;
-      float red[16];
-#pragma unroll
-      for (int f = 0; f < 16; ++f) red[f] = acc[f];
-      const float tot = reduce16_scatter(red);
-      const int slot = reduce16_index(lane);
-      const uint32_t id = __float_as_uint(q3.w);
-      if ((lane & 12) == 0 && (kGeom || slot != G_ZC)) {
-        const bool anum = slot >= G_A11 && slot <= G_A22;
-        atomicAdd(rgv + (int64_t)id * kGradRow + slot, anum ? tot * kInvSqrt2 : tot);
-      }
-      if (kGeom) {
-        const float nx = wave_sum_lane63(acc[G_NX]), ny = wave_sum_lane63(acc[G_NY]),
-                    nz = wave_sum_lane63(acc[G_NZ]);
-        if (lane == 63) {
-          float* w = rgn + (int64_t)id * kGradNrm;
-          atomicAdd(w, nx);
-          atomicAdd(w + 1, ny);
-          atomicAdd(w + 2, nz);
-        }
-      }
+      if (!any) continue;
+      bwd_commit<kGeom>(acc, lane, slot, sc, q4.w, rgv, rgn, __float_as_uint(q3.w));
     }
     __syncthreads();
     top = lo;
@@ -708,41 +745,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   const int t = (int)(b % (uint32_t)a.tiles);
   const int tx = t % a.tiles_x, ty = t / a.tiles_x;
   const DevCam& c = a.cams.c[lv];
-  const int W = c.W, H = c.H;
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
   const int ox = tx * kTile, oy = ty * kTile;
   const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
   const int64_t vn = (int64_t)v * a.n;
-  const int64_t HW = (int64_t)W * H;
   float* rgv = A.rg.row + (int64_t)v * a.n * kGradRow;
   float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
 
   BwdState p[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-    const bool in = px < W && py < H;
-    const int64_t pp = in ? (int64_t)py * W + px : 0;
-    const int64_t vp = (int64_t)v * HW + pp;
-    const int64_t v3 = (int64_t)v * 3 * HW + pp;
-    p[k].last = in ? min(max(a.img.last[vp], start), end) : start;
-    p[k].med = in ? a.img.med[vp] : 0xffffffffu;
-    p[k].Tf = in ? a.img.T_final[vp] : 1.f;
-    p[k].T = p[k].Tf;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      p[k].GC[ch] = in ? ldg0(A.up.d_rgb, v3 + ch * HW) : 0.f;
-      p[k].GS[ch] = in ? ldg0(A.up.d_rgb_ssim, v3 + ch * HW) : 0.f;
-      p[k].GN[ch] = kGeom && in ? ldg0(A.up.d_normal, v3 + ch * HW) : 0.f;
-      p[k].SC[ch] = p[k].Tf * c.bg[ch];
-      p[k].SN[ch] = 0.f;
-    }
-    p[k].GD = kGeom && in ? ldg0(A.up.d_depth, vp) : 0.f;
-    p[k].GM = kGeom && in ? ldg0(A.up.d_depth_med, vp) : 0.f;
-    p[k].GA = kGeom && in ? ldg0(A.up.d_alpha, vp) : 0.f;
-    p[k].SD = 0.f;
-  }
+  for (int k = 0; k < 4; ++k) bwd_init<kGeom>(A, c, v, ox + lx + 8 * (k & 1), oy + ly + 8 * (k >> 1), start, end, p[k]);
   // per-quadrant wave maxima of 'last': quadrant k has nothing to walk at or above qhi[k]
   uint32_t qhi[4];
 #pragma unroll
@@ -753,6 +766,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   }
   const uint32_t hi = max(max(qhi[0], qhi[1]), max(qhi[2], qhi[3]));
   const float lx0 = (float)lx + 0.5f, ly0 = (float)ly + 0.5f;
+  const int slot = reduce16_index(lane);
+  const float sc = slot_scale(slot);
 
   for (uint32_t top = hi; top > start;) {
     const uint32_t lo = top - start > 64u ? top - 64u : start;
@@ -776,29 +791,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
       if (m & 2u) bwd_px<1, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[1], acc, any);
       if (m & 4u) bwd_px<2, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[2], acc, any);
       if (m & 8u) bwd_px<3, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[3], acc, any);
-      if (__ballot(any) == 0) continue;
-      // slots 0..15 (fields G_CX..G_ZC) by reduce-scatter: one atomic instruction, one lane per field
-      float red[16];
-#pragma unroll
-      for (int f = 0; f < 16; ++f) red[f] = acc[f];
-      const float tot = reduce16_scatter(red);
-      const int slot = reduce16_index(lane);
-      const uint32_t id = __float_as_uint(q3.w);
-      if ((lane & 12) == 0 && (kGeom || slot != G_ZC)) {
-        // the staged numerator coefficients carry 1/sqrt(2)
-        const bool anum = slot >= G_A11 && slot <= G_A22;
-        atomicAdd(rgv + (int64_t)id * kGradRow + slot, anum ? tot * kInvSqrt2 : tot);
-      }
-      if (kGeom) {
-        const float nx = wave_sum_lane63(acc[G_NX]), ny = wave_sum_lane63(acc[G_NY]),
-                    nz = wave_sum_lane63(acc[G_NZ]);
-        if (lane == 63) {
-          float* q = rgn + (int64_t)id * kGradNrm;
-          atomicAdd(q, nx);
-          atomicAdd(q + 1, ny);
-          atomicAdd(q + 2, nz);
-        }
-      }
+      if (!any) continue;
+      bwd_commit<kGeom>(acc, lane, slot, sc, q4.w, rgv, rgn, __float_as_uint(q3.w));
     }
     __syncthreads();
     top = lo;
