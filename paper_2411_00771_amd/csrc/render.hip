@@ -56,12 +56,25 @@ __device__ __forceinline__ uint32_t tile_of_block(const RenderArgs& a) {
 
 __device__ __forceinline__ bool quadrant_block(const RenderArgs& a) { return blockIdx.x < 4u * a.n_split; }
 
-// LDS record, five float4 and the quadrant mask:
+// LDS record, five float4 (the quadrant masks of the 64 staged entries travel as wave ballots):
 //   q0 = (cx, cy, a11 / sqrt2, a12 / sqrt2)     q1 = (a21 / sqrt2, a22 / sqrt2, w0, w1)
 //   q2 = (w2, log2 o, z_c, z_c * w0)           q3 = (r, g, b, id)      q4 = (nx, ny, nz, 1 / o)
 struct Stage {
   float4 q[64][5];
-  uint32_t qm[64];
+};
+
+// Bit j of qb[k]: staged entry j reaches quadrant k (one ballot per quadrant of the lanes' masks).
+struct QuadBits {
+  uint64_t qb[4];
+  __device__ __forceinline__ void from_lanes(uint32_t m) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qb[k] = __ballot((m >> k) & 1u);
+  }
+  // the 4-bit quadrant mask of entry j
+  __device__ __forceinline__ uint32_t at(int j) const {
+    return (uint32_t)((qb[0] >> j) & 1u) | (uint32_t)((qb[1] >> j) & 1u) << 1 |
+           (uint32_t)((qb[2] >> j) & 1u) << 2 | (uint32_t)((qb[3] >> j) & 1u) << 3;
+  }
 };
 
 // Quadrants (bits of 'm') in which some pixel sample can reach alpha >= 1/255 (reach_setup / reach_cell).
@@ -75,16 +88,14 @@ __device__ __forceinline__ uint32_t reach_quadrants(uint32_t m, const float4& q0
   return out;
 }
 
-// qmask (optional): the forward's per-entry mask of quadrants with a contributing pixel, ANDed in;
-// without it the quadrants the surfel cannot reach are dropped by reach_quadrants.
-__device__ __forceinline__ void stage_record(Stage& s, int lane, const float* rec, int64_t vn, int64_t n, uint32_t id,
-                                             int ox, int oy, const uint8_t* qmask, uint32_t idx) {
+// Returns the entry's quadrant mask.  qmask (optional): the forward's per-entry mask of quadrants with a
+// contributing pixel, ANDed in; without it the quadrants the surfel cannot reach are dropped by
+// reach_quadrants.
+__device__ __forceinline__ uint32_t stage_record(Stage& s, int lane, const float* rec, int64_t vn, int64_t n,
+                                                 uint32_t id, int ox, int oy, const uint8_t* qmask, uint32_t idx) {
   // an entry no pixel of the forward took reaches no quadrant here: its record is not read at all
   const uint32_t qm = qmask ? qmask[idx] : 0xfu;
-  if (qm == 0u) {
-    s.qm[lane] = 0u;
-    return;
-  }
+  if (qm == 0u) return 0u;
   // an id outside [0, n) (never produced by the binning) stages a record that reaches no quadrant
   const bool valid = (int64_t)id < n;
   const float4* r = (const float4*)(rec + (size_t)(vn + (valid ? id : 0u)) * kRec);
@@ -109,7 +120,7 @@ __device__ __forceinline__ void stage_record(Stage& s, int lane, const float* re
   }
   if (qmask) m &= qm;
   else if (m) m = reach_quadrants(m, q0, q1, r2.z, r4.w);
-  s.qm[lane] = valid ? m : 0u;
+  return valid ? m : 0u;
 }
 
 // Per-surfel terms of a lane at its quadrant-0 pixel; pixel k sits at (xr0 + 8 (k & 1), yr0 + 8 (k >> 1))
@@ -276,14 +287,15 @@ __device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& 
   bool live = __ballot(f.T > 0.f) != 0;
   for (uint32_t base = start; base < end && live; base += 64) {
     const uint32_t idx = base + lane;
-    if (idx < end) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0);
+    const uint32_t qm = idx < end ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0) : 0u;
+    const uint64_t qbq = __ballot((qm >> q) & 1u);  // bit j: staged entry j reaches quadrant q
     __syncthreads();
     const int cnt = (int)min(64u, end - base);
     int reached = cnt;
     uint64_t cqq = 0;
     for (int j = 0; j < cnt; ++j) {
       if (kCount) n_eval += f.T > 0.f ? 1u : 0u;
-      if ((uniform(s.qm[j]) >> q) & 1u) {
+      if ((qbq >> j) & 1u) {
         const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
         LaneTerms lt;
         lane_terms(lx0, ly0, q0, q1, q2, lt);
@@ -395,7 +407,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   uint32_t qlive = live_quadrants(f);
   for (uint32_t base = start; base < end && qlive != 0; base += 64) {
     const uint32_t idx = base + lane;
-    if (idx < end) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0);
+    QuadBits qb;
+    qb.from_lanes(idx < end ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0) : 0u);
     __syncthreads();
     const int cnt = (int)min(64u, end - base);
     int reached = cnt;  // entries of this chunk the wave evaluated
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) n_eval += f[k].T > 0.f ? 1u : 0u;
       }
-      const uint32_t m = uniform(s.qm[j]) & qlive;
+      const uint32_t m = qb.at(j) & qlive;
       if (m != 0) {
         const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
         LaneTerms lt;
@@ -702,10 +715,11 @@ __device__ __forceinline__ void render_bwd_quadrant(const BwdArgs& A, Stage& s, 
   for (uint32_t top = hi; top > start;) {
     const uint32_t lo = top - start > 64u ? top - 64u : start;
     const uint32_t idx = lo + lane;
-    if (idx < top) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx);
+    const uint32_t qm = idx < top ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx) : 0u;
+    const uint64_t qbq = __ballot((qm >> q) & 1u);
     __syncthreads();
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
-      if (!((uniform(s.qm[j]) >> q) & 1u)) continue;
+      if (!((qbq >> j) & 1u)) continue;
       const uint32_t e_idx = lo + (uint32_t)j;
       const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
       LaneTerms lt;
@@ -772,11 +786,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   for (uint32_t top = hi; top > start;) {
     const uint32_t lo = top - start > 64u ? top - 64u : start;
     const uint32_t idx = lo + lane;
-    if (idx < top) stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx);
+    QuadBits qb;
+    qb.from_lanes(idx < top ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx) : 0u);
     __syncthreads();
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
       const uint32_t e_idx = lo + (uint32_t)j;
-      uint32_t m = uniform(s.qm[j]);
+      uint32_t m = qb.at(j);
 #pragma unroll
       for (int k = 0; k < 4; ++k) m &= e_idx < qhi[k] ? 0xfu : ~(1u << k);
       if (m == 0) continue;
