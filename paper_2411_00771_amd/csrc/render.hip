@@ -37,24 +37,32 @@ struct RenderArgs {
   float* cws;   // contribution mode: [V][n] pairs (sum of alpha^gamma T^(1-gamma), pixel count)
   float gamma;
   const uint32_t* order;  // launch order of this view chunk (heaviest tiles first), or null
-  uint32_t n_split;       // the first n_split tiles of 'order' run as four quadrant blocks each
+  uint32_t n_q, n_h;      // the first n_q tiles of 'order' run as four quadrant blocks, the next n_h as two halves
 };
 
-// Block -> (local view, tile) index: the bin_sort's heaviest-first order when present (bounded, so a
-// stale order cannot leave the launch), else the XCD-aware spatial mapping.
-// With a split prefix the launch has 3 n_split extra blocks: blocks [0, 4 n_split) are the quadrant blocks
-// of the n_split heaviest tiles (tile order[i >> 2], quadrant i & 3), the rest run whole tiles.
-__device__ __forceinline__ uint32_t tile_of_block(const RenderArgs& a) {
-  const uint32_t tiles = gridDim.x - 3u * a.n_split;
-  if (a.order) {
-    const uint32_t i = blockIdx.x < 4u * a.n_split ? blockIdx.x >> 2 : blockIdx.x - 3u * a.n_split;
-    const uint32_t b = a.order[i];
-    return b < tiles ? b : tiles - 1u;
+// Block -> (local view, tile) index and quadrant subset.  Without a launch order: the XCD-aware spatial
+// mapping, whole tiles.  With one (the bin_sort's heaviest-first order; bounded, so a stale order cannot
+// leave the launch), the n_q heaviest tiles run as four single-quadrant blocks each (blocks [0, 4 n_q)),
+// the next n_h as two halves (top 0x3, bottom 0xc; the following 2 n_h blocks), the rest whole; the
+// launch has 3 n_q + n_h blocks more than tiles.
+__device__ __forceinline__ uint32_t tile_of_block(const RenderArgs& a, uint32_t& sub) {
+  const uint32_t bid = blockIdx.x, tiles = gridDim.x - 3u * a.n_q - a.n_h;
+  sub = 0xfu;
+  if (!a.order) return xcd_remap(bid, tiles);
+  uint32_t i;
+  if (bid < 4u * a.n_q) {
+    i = bid >> 2;
+    sub = 1u << (bid & 3u);
+  } else if (bid < 4u * a.n_q + 2u * a.n_h) {
+    const uint32_t r = bid - 4u * a.n_q;
+    i = a.n_q + (r >> 1);
+    sub = (r & 1u) ? 0xcu : 0x3u;
+  } else {
+    i = bid - 3u * a.n_q - a.n_h;
   }
-  return xcd_remap(blockIdx.x, tiles);
+  const uint32_t b = a.order[i];
+  return b < tiles ? b : tiles - 1u;
 }
-
-__device__ __forceinline__ bool quadrant_block(const RenderArgs& a) { return blockIdx.x < 4u * a.n_split; }
 
 // LDS record, five float4 (the quadrant masks of the 64 staged entries travel as wave ballots):
 //   q0 = (cx, cy, a11 / sqrt2, a12 / sqrt2)     q1 = (a21 / sqrt2, a22 / sqrt2, w0, w1)
@@ -244,139 +252,28 @@ __device__ __forceinline__ bool fwd_px(const Px& e, const float4& q2, const floa
   return true;
 }
 
-// Quadrants of the tile with a running pixel (wave-uniform bit mask).
+// Quadrants (of the subset kSub) with a running pixel (wave-uniform bit mask).
+template <uint32_t kSub>
 __device__ __forceinline__ uint32_t live_quadrants(const FwdState (&f)[4]) {
   uint32_t m = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) m |= (__ballot(f[k].T > 0.f) != 0 ? 1u : 0u) << k;
+  for (int k = 0; k < 4; ++k)
+    if ((kSub >> k) & 1u) m |= (__ballot(f[k].T > 0.f) != 0 ? 1u : 0u) << k;
   return m;
 }
 
+// Forward of the quadrants kSub of one tile (bit k: 8x8 quadrant k).  kSub = 0xf is the whole tile, a lane
+// holding one pixel in each quadrant; a heavy tile runs as two halves (0x3, 0xc) or four single quadrants
+// in separate waves.  Every subset runs the per-quadrant arithmetic of the whole tile (eval_px<k> from
+// the lane terms at the quadrant-0 pixel), so the decisions do not depend on the split.  The reverse
+// pass's per-entry quadrant bits go to img.qmask: a plain byte store for a whole tile, an atomic OR on
+// the entry's word for a split one (its waves share the byte, which is cleared before the launch).
 // kCount: instead of images, count the (pixel, list entry) pairs of the method (every entry a running
 // pixel meets, quadrant mask or not), the contributing pairs, and the pairs the reverse walks.
-// Forward of one 8x8 quadrant q of a heavy tile (one pixel per lane).  Same arithmetic and decisions as the
-// whole-tile path's quadrant q; the reverse pass's quadrant bit
-// goes into img.qmask by an atomic OR on the entry's word (the four quadrant blocks share the byte,
-// which is cleared before the launch).
-template <bool kCount, bool kMask, bool kContrib, int q>
-__device__ __forceinline__ void render_fwd_quadrant(const RenderArgs& a, Stage& s, uint32_t b) {
-  const int lv = (int)(b / (uint32_t)a.tiles);
-  const int v = a.cams.v0 + lv;
-  const int t = (int)(b % (uint32_t)a.tiles);
-  const int tx = t % a.tiles_x, ty = t / a.tiles_x;
-  const DevCam& c = a.cams.c[lv];
-  const int W = c.W, H = c.H;
-  const int lane = threadIdx.x;
-  const int lx = (lane & 7) + 8 * (q & 1), ly = (lane >> 3) + 8 * (q >> 1);
-  const int ox = tx * kTile, oy = ty * kTile;
-  const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
-  const int64_t vn = (int64_t)v * a.n;
-  const int px = ox + lx, py = oy + ly;
-  const bool in = px < W && py < H;
-  FwdState f;
-  f.T = in ? 1.f : -1.f;
-  f.D = f.Dm = 0.f;
-  f.last = start - 1u;
-  f.med = 0xffffffffu;
-  f.C[0] = f.C[1] = f.C[2] = 0.f;
-  f.N[0] = f.N[1] = f.N[2] = 0.f;
-  unsigned long long n_eval = 0, n_con = 0;
-  // lane terms at the quadrant-0 pixel and the quadrant's offset applied by eval_px<q>: the arithmetic of
-  // the whole-tile path, so both paths (and the reverse pass) take bit-identical decisions
-  const float lx0 = (float)(lane & 7) + 0.5f, ly0 = (float)(lane >> 3) + 0.5f;
-  bool live = __ballot(f.T > 0.f) != 0;
-  for (uint32_t base = start; base < end && live; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t qm = idx < end ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0) : 0u;
-    const uint64_t qbq = __ballot((qm >> q) & 1u);  // bit j: staged entry j reaches quadrant q
-    __syncthreads();
-    const int cnt = (int)min(64u, end - base);
-    int reached = cnt;
-    uint64_t cqq = 0;
-    for (int j = 0; j < cnt; ++j) {
-      if (kCount) n_eval += f.T > 0.f ? 1u : 0u;
-      if ((qbq >> j) & 1u) {
-        const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
-        LaneTerms lt;
-        lane_terms(lx0, ly0, q0, q1, q2, lt);
-        Px e;
-        eval_px<q>(lt, q2.y, e);
-        float csum = 0.f, ccnt = 0.f;
-        if (fwd_px<kContrib>(e, q2, q3, q4, lane_copy(base + (uint32_t)j), f, n_con, a.gamma, csum, ccnt)) {
-          if (kMask) cqq |= 1ull << j;
-          if (kContrib) {
-            const float ts = wave_sum_lane63(csum), tc = wave_sum_lane63(ccnt);
-            if (lane == 63 && tc > 0.f) {
-              float* w = a.cws + 2 * (vn + (int64_t)__float_as_uint(q3.w));
-              atomicAdd(w, ts);
-              atomicAdd(w + 1, tc);
-            }
-          }
-        }
-      }
-      if ((j & 15) == 15 && __ballot(f.T > 0.f) == 0) {
-        reached = j + 1;
-        break;
-      }
-    }
-    if (kMask && lane < reached && ((cqq >> lane) & 1u)) {
-      uint32_t* word = (uint32_t*)(a.img.qmask + (idx & ~3u));
-      atomicOr(word, 1u << (8u * (idx & 3u) + (uint32_t)q));
-    }
-    live = __ballot(f.T > 0.f) != 0;
-    __syncthreads();
-  }
-  if (kContrib) return;
-  if (kCount) {
-    const unsigned long long n_bwd = in ? f.last + 1u - start : 0u;
-    atomicAdd(a.counters + 0, n_eval);
-    atomicAdd(a.counters + 1, n_con);
-    atomicAdd(a.counters + 2, n_bwd);
-    return;
-  }
-  if (!in) return;
-  const int64_t HW = (int64_t)W * H;
-  const cgv2_image& im = a.img;
-  const int64_t p = (int64_t)py * W + px;
-  const float T = fabsf(f.T);
-  if (im.rgb) {
-    float* o = im.rgb + (int64_t)v * 3 * HW + p;
-    o[0] = fmaf(T, c.bg[0], f.C[0]);
-    o[HW] = fmaf(T, c.bg[1], f.C[1]);
-    o[2 * HW] = fmaf(T, c.bg[2], f.C[2]);
-  }
-  if (im.normal) {
-    float* o = im.normal + (int64_t)v * 3 * HW + p;
-    o[0] = f.N[0];
-    o[HW] = f.N[1];
-    o[2 * HW] = f.N[2];
-  }
-  const int64_t vp = (int64_t)v * HW + p;
-  if (im.depth) im.depth[vp] = f.D;
-  if (im.depth_med) im.depth_med[vp] = f.Dm;
-  if (im.alpha) im.alpha[vp] = 1.f - T;
-  if (im.T_final) im.T_final[vp] = T;
-  if (im.last) im.last[vp] = f.last + 1u;
-  if (im.med) im.med[vp] = f.med;
-}
-
-// kMask: also write the per-entry quadrant mask img.qmask for the reverse pass.
 // kContrib: instead of images, add each surfel's contribution sums (Sec. 3.3, Eq. 3) of this view into
-// a.cws, one wave reduction and one atomic pair per (surfel, tile).
-template <bool kCount, bool kMask, bool kContrib>
-__global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
-  __shared__ Stage s;
-  const uint32_t b = tile_of_block(a);
-  if (*a.status != 0) return;
-  if (quadrant_block(a)) {
-    switch (blockIdx.x & 3u) {
-      case 0: render_fwd_quadrant<kCount, kMask, kContrib, 0>(a, s, b); break;
-      case 1: render_fwd_quadrant<kCount, kMask, kContrib, 1>(a, s, b); break;
-      case 2: render_fwd_quadrant<kCount, kMask, kContrib, 2>(a, s, b); break;
-      default: render_fwd_quadrant<kCount, kMask, kContrib, 3>(a, s, b); break;
-    }
-    return;
-  }
+// a.cws, one wave reduction and one atomic pair per (surfel, tile or split block).
+template <bool kCount, bool kMask, bool kContrib, uint32_t kSub>
+__device__ __forceinline__ void render_fwd_tile(const RenderArgs& a, Stage& s, uint32_t b) {
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
@@ -394,7 +291,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-    f[k].T = px < W && py < H ? 1.f : -1.f;
+    f[k].T = ((kSub >> k) & 1u) && px < W && py < H ? 1.f : -1.f;
     f[k].D = 0.f;
     f[k].Dm = 0.f;
     f[k].last = start - 1u;
@@ -404,7 +301,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
   }
   const float lx0 = (float)lx + 0.5f, ly0 = (float)ly + 0.5f;
   uint8_t* qmask = kMask ? a.img.qmask : nullptr;
-  uint32_t qlive = live_quadrants(f);
+  uint32_t qlive = live_quadrants<kSub>(f);
   for (uint32_t base = start; base < end && qlive != 0; base += 64) {
     const uint32_t idx = base + lane;
     QuadBits qb;
@@ -413,11 +310,12 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     const int cnt = (int)min(64u, end - base);
     int reached = cnt;  // entries of this chunk the wave evaluated
     // bit j of cq[k]: quadrant k had a taking pixel at entry base + j (scalar registers)
-    uint64_t cq0 = 0, cq1 = 0, cq2 = 0, cq3 = 0;
+    uint64_t cq[4] = {0, 0, 0, 0};
     for (int j = 0; j < cnt; ++j) {
       if (kCount) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) n_eval += f[k].T > 0.f ? 1u : 0u;
+        for (int k = 0; k < 4; ++k)
+          if ((kSub >> k) & 1u) n_eval += f[k].T > 0.f ? 1u : 0u;
       }
       const uint32_t m = qb.at(j) & qlive;
       if (m != 0) {
@@ -425,29 +323,21 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         LaneTerms lt;
         lane_terms(lx0, ly0, q0, q1, q2, lt);
         const uint32_t e_idx = lane_copy(base + (uint32_t)j);
-        const uint64_t bit = 1ull << j;
         float csum = 0.f, ccnt = 0.f;
         bool took = false;
-        Px e0, e1, e2, e3;
-        eval_px<0>(lt, q2.y, e0);
-        eval_px<1>(lt, q2.y, e1);
-        eval_px<2>(lt, q2.y, e2);
-        eval_px<3>(lt, q2.y, e3);
-        if ((m & 1u) && fwd_px<kContrib>(e0, q2, q3, q4, e_idx, f[0], n_con, a.gamma, csum, ccnt)) {
-          took = true;
-          if (kMask) cq0 |= bit;
-        }
-        if ((m & 2u) && fwd_px<kContrib>(e1, q2, q3, q4, e_idx, f[1], n_con, a.gamma, csum, ccnt)) {
-          took = true;
-          if (kMask) cq1 |= bit;
-        }
-        if ((m & 4u) && fwd_px<kContrib>(e2, q2, q3, q4, e_idx, f[2], n_con, a.gamma, csum, ccnt)) {
-          took = true;
-          if (kMask) cq2 |= bit;
-        }
-        if ((m & 8u) && fwd_px<kContrib>(e3, q2, q3, q4, e_idx, f[3], n_con, a.gamma, csum, ccnt)) {
-          took = true;
-          if (kMask) cq3 |= bit;
+        Px e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (!((kSub >> k) & 1u)) continue;
+          // (evaluated where it is used: the compiler sinks each pixel's evaluation into its branch)
+          if (k == 0) eval_px<0>(lt, q2.y, e[0]);
+          if (k == 1) eval_px<1>(lt, q2.y, e[1]);
+          if (k == 2) eval_px<2>(lt, q2.y, e[2]);
+          if (k == 3) eval_px<3>(lt, q2.y, e[3]);
+          if (((m >> k) & 1u) && fwd_px<kContrib>(e[k], q2, q3, q4, e_idx, f[k], n_con, a.gamma, csum, ccnt)) {
+            took = true;
+            if (kMask) cq[k] |= 1ull << j;
+          }
         }
         if (kContrib && took) {
           const float ts = wave_sum_lane63(csum), tc = wave_sum_lane63(ccnt);
@@ -459,7 +349,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
         }
       }
       if ((j & 15) == 15) {
-        qlive = live_quadrants(f);
+        qlive = live_quadrants<kSub>(f);
         if (qlive == 0) {
           reached = j + 1;
           break;
@@ -467,10 +357,13 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
       }
     }
     // entries past 'reached' lie beyond every pixel's 'last': the reverse pass never reads them
-    if (kMask && lane < reached)
-      qmask[idx] = (uint8_t)(((cq0 >> lane) & 1u) | (((cq1 >> lane) & 1u) << 1) | (((cq2 >> lane) & 1u) << 2) |
-                             (((cq3 >> lane) & 1u) << 3));
-    qlive = live_quadrants(f);
+    if (kMask && lane < reached) {
+      const uint32_t bits = (uint32_t)((cq[0] >> lane) & 1u) | (uint32_t)((cq[1] >> lane) & 1u) << 1 |
+                            (uint32_t)((cq[2] >> lane) & 1u) << 2 | (uint32_t)((cq[3] >> lane) & 1u) << 3;
+      if (kSub == 0xfu) qmask[idx] = (uint8_t)bits;
+      else if (bits) atomicOr((uint32_t*)(qmask + (idx & ~3u)), bits << (8u * (idx & 3u)));
+    }
+    qlive = live_quadrants<kSub>(f);
     __syncthreads();
   }
   if (kContrib) return;
@@ -479,7 +372,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-      if (px < W && py < H) n_bwd += f[k].last + 1u - start;
+      if (((kSub >> k) & 1u) && px < W && py < H) n_bwd += f[k].last + 1u - start;
     }
     atomicAdd(a.counters + 0, n_eval);
     atomicAdd(a.counters + 1, n_con);
@@ -491,7 +384,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int px = ox + lx + 8 * (k & 1), py = oy + ly + 8 * (k >> 1);
-    if (!(px < W && py < H)) continue;
+    if (!((kSub >> k) & 1u) || !(px < W && py < H)) continue;
     const int64_t p = (int64_t)py * W + px;
     const float T = fabsf(f[k].T);
     if (im.rgb) {
@@ -513,6 +406,23 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
     if (im.T_final) im.T_final[vp] = T;
     if (im.last) im.last[vp] = f[k].last + 1u;
     if (im.med) im.med[vp] = f[k].med;
+  }
+}
+
+template <bool kCount, bool kMask, bool kContrib>
+__global__ __launch_bounds__(64) void k_render_fwd(RenderArgs a) {
+  __shared__ Stage s;
+  uint32_t sub;
+  const uint32_t b = tile_of_block(a, sub);
+  if (*a.status != 0) return;
+  switch (sub) {
+    case 0x1u: render_fwd_tile<kCount, kMask, kContrib, 0x1u>(a, s, b); break;
+    case 0x2u: render_fwd_tile<kCount, kMask, kContrib, 0x2u>(a, s, b); break;
+    case 0x4u: render_fwd_tile<kCount, kMask, kContrib, 0x4u>(a, s, b); break;
+    case 0x8u: render_fwd_tile<kCount, kMask, kContrib, 0x8u>(a, s, b); break;
+    case 0x3u: render_fwd_tile<kCount, kMask, kContrib, 0x3u>(a, s, b); break;
+    case 0xcu: render_fwd_tile<kCount, kMask, kContrib, 0xcu>(a, s, b); break;
+    default: render_fwd_tile<kCount, kMask, kContrib, 0xfu>(a, s, b); break;
   }
 }
 
@@ -688,72 +598,13 @@ __device__ __forceinline__ void bwd_commit(float (&acc)[kGradFields], int lane, 
   }
 }
 
-// Reverse pass over one 8x8 quadrant q of a heavy tile (one pixel per lane): the whole-tile path's
-// quadrant q (same arithmetic and decisions), with its record gradients added per (surfel, quadrant).
-template <bool kGeom, int q>
-__device__ __forceinline__ void render_bwd_quadrant(const BwdArgs& A, Stage& s, uint32_t b) {
-  const RenderArgs& a = A.r;
-  const int lv = (int)(b / (uint32_t)a.tiles);
-  const int v = a.cams.v0 + lv;
-  const int t = (int)(b % (uint32_t)a.tiles);
-  const int tx = t % a.tiles_x, ty = t / a.tiles_x;
-  const DevCam& c = a.cams.c[lv];
-  const int lane = threadIdx.x;
-  const int ox = tx * kTile, oy = ty * kTile;
-  const uint32_t start = a.ranges[(int64_t)v * a.tiles + t], end = a.ranges[(int64_t)v * a.tiles + t + 1];
-  const int64_t vn = (int64_t)v * a.n;
-  float* rgv = A.rg.row + (int64_t)v * a.n * kGradRow;
-  float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
-  BwdState p;
-  bwd_init<kGeom>(A, c, v, ox + (lane & 7) + 8 * (q & 1), oy + (lane >> 3) + 8 * (q >> 1), start, end, p);
-  uint32_t h = p.last;
-  for (int off = 1; off < 64; off <<= 1) h = max(h, __shfl_xor(h, off));
-  const uint32_t hi = uniform(h);
-  const float lx0 = (float)(lane & 7) + 0.5f, ly0 = (float)(lane >> 3) + 0.5f;
-  const int slot = reduce16_index(lane);
-  const float sc = slot_scale(slot);
-  for (uint32_t top = hi; top > start;) {
-    const uint32_t lo = top - start > 64u ? top - 64u : start;
-    const uint32_t idx = lo + lane;
-    const uint32_t qm = idx < top ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx) : 0u;
-    const uint64_t qbq = __ballot((qm >> q) & 1u);
-    __syncthreads();
-    for (int j = (int)(top - lo) - 1; j >= 0; --j) {
-      if (!((qbq >> j) & 1u)) continue;
-      const uint32_t e_idx = lo + (uint32_t)j;
-      const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
-      LaneTerms lt;
-      lane_terms(lx0, ly0, q0, q1, q2, lt);
-      float acc[kGradFields];
-#pragma unroll
-      for (int f = 0; f < kGradFields; ++f) acc[f] = 0.f;
-      bool any = false;
-      bwd_px<q, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p, acc, any);
-      if (!any) continue;
-      bwd_commit<kGeom>(acc, lane, slot, sc, q4.w, rgv, rgn, __float_as_uint(q3.w));
-    }
-    __syncthreads();
-    top = lo;
-  }
-}
-
+// Reverse pass over the quadrants kSub of one tile (as render_fwd_tile): each entry's record gradients
+// summed over the block's pixels and added per (surfel, tile or split block).
 // kGeom: depth, median-depth, normal or alpha upstream gradients are present.  Without them (the
 // photometric-loss-only case) their per-pixel state, terms and four of the reductions drop out.
-template <bool kGeom>
-__global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
-  __shared__ Stage s;
+template <bool kGeom, uint32_t kSub>
+__device__ __forceinline__ void render_bwd_tile(const BwdArgs& A, Stage& s, uint32_t b) {
   const RenderArgs& a = A.r;
-  const uint32_t b = tile_of_block(a);
-  if (*a.status != 0) return;
-  if (quadrant_block(a)) {
-    switch (blockIdx.x & 3u) {
-      case 0: render_bwd_quadrant<kGeom, 0>(A, s, b); break;
-      case 1: render_bwd_quadrant<kGeom, 1>(A, s, b); break;
-      case 2: render_bwd_quadrant<kGeom, 2>(A, s, b); break;
-      default: render_bwd_quadrant<kGeom, 3>(A, s, b); break;
-    }
-    return;
-  }
   const int lv = (int)(b / (uint32_t)a.tiles);
   const int v = a.cams.v0 + lv;
   const int t = (int)(b % (uint32_t)a.tiles);
@@ -768,12 +619,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
   float* rgn = A.rg.nrm + (int64_t)v * a.n * kGradNrm;
 
   BwdState p[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) bwd_init<kGeom>(A, c, v, ox + lx + 8 * (k & 1), oy + ly + 8 * (k >> 1), start, end, p[k]);
   // per-quadrant wave maxima of 'last': quadrant k has nothing to walk at or above qhi[k]
   uint32_t qhi[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
+    qhi[k] = start;
+    if (!((kSub >> k) & 1u)) continue;
+    bwd_init<kGeom>(A, c, v, ox + lx + 8 * (k & 1), oy + ly + 8 * (k >> 1), start, end, p[k]);
     uint32_t h = p[k].last;
     for (int off = 1; off < 64; off <<= 1) h = max(h, __shfl_xor(h, off));
     qhi[k] = uniform(h);
@@ -791,7 +643,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
     __syncthreads();
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
       const uint32_t e_idx = lo + (uint32_t)j;
-      uint32_t m = qb.at(j);
+      uint32_t m = qb.at(j) & kSub;
 #pragma unroll
       for (int k = 0; k < 4; ++k) m &= e_idx < qhi[k] ? 0xfu : ~(1u << k);
       if (m == 0) continue;
@@ -802,15 +654,32 @@ __global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) acc[f] = 0.f;
       bool any = false;
-      if (m & 1u) bwd_px<0, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[0], acc, any);
-      if (m & 2u) bwd_px<1, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[1], acc, any);
-      if (m & 4u) bwd_px<2, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[2], acc, any);
-      if (m & 8u) bwd_px<3, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[3], acc, any);
+      if ((kSub & 1u) && (m & 1u)) bwd_px<0, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[0], acc, any);
+      if ((kSub & 2u) && (m & 2u)) bwd_px<1, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[1], acc, any);
+      if ((kSub & 4u) && (m & 4u)) bwd_px<2, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[2], acc, any);
+      if ((kSub & 8u) && (m & 8u)) bwd_px<3, kGeom>(lt, q0, q1, q2, q3, q4, e_idx, p[3], acc, any);
       if (!any) continue;
       bwd_commit<kGeom>(acc, lane, slot, sc, q4.w, rgv, rgn, __float_as_uint(q3.w));
     }
     __syncthreads();
     top = lo;
+  }
+}
+
+template <bool kGeom>
+__global__ __launch_bounds__(64) void k_render_bwd(BwdArgs A) {
+  __shared__ Stage s;
+  uint32_t sub;
+  const uint32_t b = tile_of_block(A.r, sub);
+  if (*A.r.status != 0) return;
+  switch (sub) {
+    case 0x1u: render_bwd_tile<kGeom, 0x1u>(A, s, b); break;
+    case 0x2u: render_bwd_tile<kGeom, 0x2u>(A, s, b); break;
+    case 0x4u: render_bwd_tile<kGeom, 0x4u>(A, s, b); break;
+    case 0x8u: render_bwd_tile<kGeom, 0x8u>(A, s, b); break;
+    case 0x3u: render_bwd_tile<kGeom, 0x3u>(A, s, b); break;
+    case 0xcu: render_bwd_tile<kGeom, 0xcu>(A, s, b); break;
+    default: render_bwd_tile<kGeom, 0xfu>(A, s, b); break;
   }
 }
 
@@ -832,15 +701,21 @@ __global__ __launch_bounds__(256) void k_zero_visible(const uint32_t* __restrict
 
 }  // namespace cgv2
 
-// Heavy tiles split into quadrant blocks: 1 / kSplitDiv of a launch's tiles, at most kSplitMax.
+// Heavy tiles split over several waves: the 1 / kSplitDiv heaviest of a launch's tiles (at most
+// kSplitMax) into four quadrant blocks, the next 1 / kHalfDiv (at most kSplitMax; none for 0) into two
+// halves.
 #ifndef CGV2_SPLIT_DIV
-#define CGV2_SPLIT_DIV 24
+#define CGV2_SPLIT_DIV 48
+#endif
+#ifndef CGV2_HALF_DIV
+#define CGV2_HALF_DIV 12
 #endif
 constexpr int kSplitDiv = CGV2_SPLIT_DIV;
+constexpr int kHalfDiv = CGV2_HALF_DIV;
 constexpr int kSplitMax = 1024;
 
 namespace cgv2 {
-// Clears the quadrant-mask bytes of the split tiles' lists (their four quadrant blocks OR their bits in).
+// Clears the quadrant-mask bytes of the split tiles' lists (their blocks OR their bits in).
 __global__ __launch_bounds__(256) void k_clear_split_qmask(RenderArgs a) {
   if (*a.status != 0) return;  // overflowed bins: ranges may lie beyond the list arrays
   const uint32_t tiles = (uint32_t)a.cams.count * (uint32_t)a.tiles;
@@ -869,16 +744,20 @@ static cgv2::RenderArgs make_args(const cgv2_proj& p, const cgv2_bins& b, const 
   a.counters = counters;
   a.cws = nullptr;
   a.gamma = 0.f;
-  a.n_split = a.order ? (uint32_t)std::min<int64_t>((int64_t)cams.count * a.tiles / kSplitDiv, kSplitMax) : 0u;
+  const int64_t all = (int64_t)cams.count * a.tiles;
+  a.n_q = a.order ? (uint32_t)std::min<int64_t>(all / kSplitDiv, kSplitMax) : 0u;
+  a.n_h = a.order && kHalfDiv > 0 ? (uint32_t)std::min<int64_t>({all / std::max(kHalfDiv, 1), (int64_t)kSplitMax,
+                                                                   all - (int64_t)a.n_q})
+                                  : 0u;
   return a;
 }
 
 hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                   int tiles_x, int tiles_y, const cgv2_image& img, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
-  if (img.qmask && a.n_split)
-    hipLaunchKernelGGL(cgv2::k_clear_split_qmask, dim3(a.n_split), dim3(256), 0, st, a);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_q + a.n_h);
+  if (img.qmask && a.n_q + a.n_h)
+    hipLaunchKernelGGL(cgv2::k_clear_split_qmask, dim3(a.n_q + a.n_h), dim3(256), 0, st, a);
   if (img.qmask) hipLaunchKernelGGL((cgv2::k_render_fwd<false, true, false>), dim3(grid), dim3(64), 0, st, a);
   else hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
@@ -887,7 +766,7 @@ hipError_t cgv2_launch_render_fwd(const cgv2_proj& p, const cgv2_bins& b, const 
 hipError_t cgv2_launch_render_count(const cgv2_proj& p, const cgv2_bins& b, const cgv2::CamPack& cams, int64_t n,
                                     int tiles_x, int tiles_y, unsigned long long* counters, hipStream_t st) {
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, counters);
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_q + a.n_h);
   hipLaunchKernelGGL((cgv2::k_render_fwd<true, false, false>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
@@ -904,7 +783,7 @@ hipError_t cgv2_launch_render_bwd(const cgv2_proj& p, const cgv2_bins& b, const 
   A.r = make_args(p, b, cams, n, tiles_x, tiles_y, &img, nullptr);
   A.up = up;
   A.rg = rg;
-  const unsigned grid = (unsigned)((int64_t)cams.count * A.r.tiles + 3 * A.r.n_split);
+  const unsigned grid = (unsigned)((int64_t)cams.count * A.r.tiles + 3 * A.r.n_q + A.r.n_h);
   const bool geom = up.d_depth || up.d_depth_med || up.d_normal || up.d_alpha;
   if (geom) hipLaunchKernelGGL(cgv2::k_render_bwd<true>, dim3(grid), dim3(64), 0, st, A);
   else hipLaunchKernelGGL(cgv2::k_render_bwd<false>, dim3(grid), dim3(64), 0, st, A);
@@ -916,7 +795,7 @@ hipError_t cgv2_launch_contribution(const cgv2_proj& p, const cgv2_bins& b, cons
   cgv2::RenderArgs a = make_args(p, b, cams, n, tiles_x, tiles_y, nullptr, nullptr);
   a.cws = cws;
   a.gamma = gamma;
-  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_split);
+  const unsigned grid = (unsigned)((int64_t)cams.count * a.tiles + 3 * a.n_q + a.n_h);
   hipLaunchKernelGGL((cgv2::k_render_fwd<false, false, true>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
