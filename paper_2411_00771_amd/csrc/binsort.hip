@@ -212,19 +212,83 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
 }
 
 // Groups of 32 lanes take one visible surfel of view blockIdx.y each and spread its rect tiles over the
-// group, so a surfel that covers hundreds of tiles does not hold up a wave.  (Measured: 8 or 16 lanes
-// are slower on the training views, 64 saves 7 us there but costs 20 % of the served latency on the
-// 5 M-surfel 4K views; batches of 64 surfels with their tiles flattened over the lanes are slower; up to
-// 8192 workgroups per view instead of 2048 saves 3 us on the training views.)
+// group.  A group stages at most the first kFirstTiles tiles of a surfel itself; the rest of a larger rect
+// (a surfel near the camera, or a long thin one) goes to a queue of kChunkTiles-tile chunks that
+// k_stage_big spreads over all groups, so no group walks one rect for long while the others idle.
+// (Measured: 8 or 16 lanes per surfel are slower on the training views, 64 saves 7 us there but costs
+// 20 % of the served latency on the 5 M-surfel 4K views; batches of 64 surfels with their tiles
+// flattened over the lanes are slower; up to 8192 workgroups per view instead of 2048 saves 3 us.)
 constexpr int kGroup = 32;
 constexpr uint32_t kNoTile = 0xffffffffu;  // staged slot of a rect tile the surfel cannot reach
+constexpr uint32_t kChunkTiles = 4 * kGroup;
+constexpr uint32_t kFirstTiles = 2 * kChunkTiles;
+
+// One visible surfel of view v as the staging sees it.
+struct StageSurfel {
+  uint32_t tx0, ty0, w, total, o;
+  float4 r0;
+  uint64_t key;
+  Reach q;
+};
+
+__device__ __forceinline__ void stage_surfel(const uint16_t* rect, const float* rec, const uint32_t* soff, int64_t n,
+                                             int v, uint32_t i, StageSurfel& u) {
+  const int64_t vi = (int64_t)v * n + i;
+  uint32_t tx1, ty1;
+  tile_rect(rect + 4 * vi, u.tx0, u.ty0, tx1, ty1);
+  u.w = tx1 - u.tx0;
+  u.total = u.w * (ty1 - u.ty0);
+  const float4* rp = (const float4*)(rec + vi * kRec);
+  const float4 r1 = rp[1], r2 = rp[2], r4 = rp[4];
+  u.r0 = rp[0];
+  u.key = ((uint64_t)__float_as_uint(r2.w) << 32) | i;
+  reach_setup(r1.x * kInvSqrt2, r1.y * kInvSqrt2, r1.z * kInvSqrt2, r1.w * kInvSqrt2, r2.x, r2.y, r2.z, r4.w, u.q);
+  u.o = soff[vi];
+}
+
+// Rect tiles [kb, ke) of surfel u, tile k on lane kb + g + 32 j of the group: for each tile the surfel's
+// alpha >= 1/255 region reaches, a returning atomic on the tile's counter gives the entry's rank; (tile,
+// rank) and the key go to the surfel's slot o + k, a sentinel tile to the slots of the tiles it cannot
+// reach.  Four independent returning atomics are in flight per lane before their results are used.
+__device__ __forceinline__ void stage_range(const StageSurfel& u, uint32_t tbase, int tiles_x, uint32_t kb, uint32_t ke,
+                                            uint32_t g, uint32_t* __restrict__ cnt, uint2* __restrict__ st_pos,
+                                            uint64_t* __restrict__ st_key) {
+  for (uint32_t k0 = kb + g; k0 < ke; k0 += 4 * kGroup) {
+    uint32_t t[4], r[4];
+    bool keep[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k = k0 + (uint32_t)j * kGroup;
+      const uint32_t tx = u.tx0 + k % u.w, ty = u.ty0 + k / u.w;
+      t[j] = tbase + ty * tiles_x + tx;
+      // the tile-relative centre exactly as the renderer stages it
+      const float fox = (float)(tx * kTile), foy = (float)(ty * kTile);
+      keep[j] = k < ke && reach_cell(u.q, (u.r0.x - fox) + u.r0.z, (u.r0.y - foy) + u.r0.w, 0, 0, kTile);
+      r[j] = keep[j] ? atomicAdd(cnt + t[j], 1u) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k = k0 + (uint32_t)j * kGroup;
+      if (k < ke) {
+        st_pos[u.o + k] = make_uint2(keep[j] ? t[j] : kNoTile, r[j]);
+        if (keep[j]) st_key[u.o + k] = u.key;
+      }
+    }
+  }
+}
+
+// chunk queue entry: (index into 'visible', view << 16 | chunk); chunk c covers rect tiles
+// [kFirstTiles + c kChunkTiles, ... + kChunkTiles).  A surfel with T > kFirstTiles tiles queues
+// ceil((T - kFirstTiles) / kChunkTiles) < T / kChunkTiles chunks, so capacity / kChunkTiles + 1 entries
+// hold every queue whose rect slots fit the capacity (the staging does not run otherwise).
 __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect, const float* __restrict__ rec,
                                                int64_t n, int tiles_x, int tiles_per_view,
                                                const uint32_t* __restrict__ visible,
                                                const uint32_t* __restrict__ vstart,
                                                const uint32_t* __restrict__ soff, uint32_t* __restrict__ cnt,
                                                uint2* __restrict__ st_pos, uint64_t* __restrict__ st_key,
-                                               const int32_t* __restrict__ status) {
+                                               uint2* __restrict__ chunks, uint32_t* __restrict__ n_chunks,
+                                               uint32_t max_chunks, const int32_t* __restrict__ status) {
   const int v = blockIdx.y;
   if (*status != 0) return;
   const uint32_t nv = vstart[v + 1] - vstart[v];
@@ -233,44 +297,44 @@ __global__ __launch_bounds__(256) void k_stage(const uint16_t* __restrict__ rect
   const uint32_t tbase = (uint32_t)v * (uint32_t)tiles_per_view;
   for (uint32_t e = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; e < nv;
        e += gridDim.x * blockDim.x / kGroup) {
-    const uint32_t i = list[e];
-    const int64_t vi = (int64_t)v * n + i;
-    uint32_t tx0, ty0, tx1, ty1;
-    tile_rect(rect + 4 * vi, tx0, ty0, tx1, ty1);
-    const uint32_t w = tx1 - tx0, total = w * (ty1 - ty0);
-    const float4* rp = (const float4*)(rec + vi * kRec);
-    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r4 = rp[4];
-    const uint64_t key = ((uint64_t)__float_as_uint(r2.w) << 32) | i;
-    Reach q;
-    reach_setup(r1.x * kInvSqrt2, r1.y * kInvSqrt2, r1.z * kInvSqrt2, r1.w * kInvSqrt2, r2.x, r2.y, r2.z, r4.w, q);
-    const uint32_t o = soff[vi];
-    // four independent returning atomics in flight per lane before their results are used
-    for (uint32_t k0 = g; k0 < total; k0 += 4 * kGroup) {
-      uint32_t t[4], r[4];
-      bool keep[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t k = k0 + (uint32_t)j * kGroup;
-        const uint32_t tx = tx0 + k % w, ty = ty0 + k / w;
-        t[j] = tbase + ty * tiles_x + tx;
-        // the tile-relative centre exactly as the renderer stages it
-        const float fox = (float)(tx * kTile), foy = (float)(ty * kTile);
-        keep[j] = k < total && reach_cell(q, (r0.x - fox) + r0.z, (r0.y - foy) + r0.w, 0, 0, kTile);
-        r[j] = keep[j] ? atomicAdd(cnt + t[j], 1u) : 0u;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t k = k0 + (uint32_t)j * kGroup;
-        if (k < total) {
-          st_pos[o + k] = make_uint2(keep[j] ? t[j] : kNoTile, r[j]);
-          if (keep[j]) st_key[o + k] = key;
-        }
-      }
+    StageSurfel u;
+    stage_surfel(rect, rec, soff, n, v, list[e], u);
+    stage_range(u, tbase, tiles_x, 0u, min(u.total, kFirstTiles), g, cnt, st_pos, st_key);
+    if (u.total > kFirstTiles) {
+      const uint32_t nc = (u.total - kFirstTiles + kChunkTiles - 1) / kChunkTiles;
+      uint32_t base = 0;
+      if (g == 0) base = atomicAdd(n_chunks, nc);
+      base = __shfl(base, (int)(threadIdx.x & 63u & ~(uint32_t)(kGroup - 1)), 64);
+      for (uint32_t c = g; c < nc; c += kGroup)
+        if (base + c < max_chunks) chunks[base + c] = make_uint2(vstart[v] + e, ((uint32_t)v << 16) | c);
     }
   }
 }
 
-// One workgroup: ranges[t] = exclusive prefix sum of cnt (m tile counters), ranges[m] = total.
+// The queued chunks of the large rects, one chunk per group.
+__global__ __launch_bounds__(256) void k_stage_big(const uint16_t* __restrict__ rect, const float* __restrict__ rec,
+                                                   int64_t n, int tiles_x, int tiles_per_view,
+                                                   const uint32_t* __restrict__ visible,
+                                                   const uint32_t* __restrict__ soff, uint32_t* __restrict__ cnt,
+                                                   uint2* __restrict__ st_pos, uint64_t* __restrict__ st_key,
+                                                   const uint2* __restrict__ chunks,
+                                                   const uint32_t* __restrict__ n_chunks, uint32_t max_chunks,
+                                                   const int32_t* __restrict__ status) {
+  if (*status != 0) return;
+  const uint32_t nc = min(*n_chunks, max_chunks);
+  const uint32_t g = threadIdx.x % kGroup;
+  for (uint32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; it < nc;
+       it += gridDim.x * blockDim.x / kGroup) {
+    const uint2 c = chunks[it];
+    const int v = (int)(c.y >> 16);
+    StageSurfel u;
+    stage_surfel(rect, rec, soff, n, v, visible[c.x], u);
+    const uint32_t kb = kFirstTiles + (c.y & 0xffffu) * kChunkTiles;
+    stage_range(u, (uint32_t)v * (uint32_t)tiles_per_view, tiles_x, kb, min(u.total, kb + kChunkTiles), g, cnt,
+                st_pos, st_key);
+  }
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const uint32_t* __restrict__ cnt, int64_t m,
                                                           uint32_t* __restrict__ ranges) {
   __shared__ uint64_t lds[2 * kScanWaves];
@@ -633,7 +697,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
 static int64_t scan_blocks(int64_t m) { return (m + cgv2::kScanChunk - 1) / cgv2::kScanChunk; }
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off) {
-  // off: [0] tile counters (u32, m) followed by the big-list count, [1] chunk sums of the surfel
+  // off: [0] tile counters (u32, m) followed by the big-list and chunk-queue counts, [1] chunk sums of the surfel
   //      scan (2 x u64 arrays), [2] big_list (u32, m), [3] scan totals (u64 x 2), [4] keys (u64,
   //      capacity), [5] staged keys / merge scratch (u64, capacity), [6] staged (tile, rank) (u32 x 2,
   //      capacity), [7] surfel offsets (u32, V n + 1), [8] chunk sums of the tile scan (u64)
@@ -642,7 +706,7 @@ size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, siz
   const int64_t nsb = scan_blocks(vn > 0 ? vn : 1);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
-  off[0] = take(4 * (size_t)(m + 1));
+  off[0] = take(4 * (size_t)(m + 2));
   off[1] = take(16 * (size_t)(nsb + 1));
   off[2] = take(4 * (size_t)m);
   off[3] = take(64);
@@ -654,6 +718,8 @@ size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, siz
   // [9] per-chunk bucket counts of the launch order (one view chunk at a time)
   const int64_t per = (int64_t)std::min(V, cgv2::kMaxViews) * tiles;
   off[9] = take(4 * (size_t)cgv2::kOrdBuckets * (size_t)((per + cgv2::kOrdChunk - 1) / cgv2::kOrdChunk + 1));
+  // [10] the chunk queue of the large rects (see k_stage)
+  off[10] = take(8 * (size_t)(capacity / cgv2::kChunkTiles + 1));
   return o;
 }
 
@@ -677,11 +743,14 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   uint64_t* stk = (uint64_t*)(w + off[5]);
   uint2* stp = (uint2*)(w + off[6]);
   uint32_t* soff = (uint32_t*)(w + off[7]);
+  uint32_t* n_chunks = cnt + m + 1;
+  uint2* chunks = (uint2*)(w + off[10]);
+  const uint32_t max_chunks = (uint32_t)std::min<int64_t>(b.capacity / kChunkTiles + 1, 0xffffffffll);
   if (n > 0) {
     // surfel offsets, visible lists (consumed by the staging here and by the reverse pass), total and
     // overflow check; the tile counters and the big-list count are zeroed on the way
     hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis,
-                       cnt, m + 1);
+                       cnt, m + 2);
     // up to kScanBlock chunks each apply workgroup adds up the chunk sums before it itself
     const int local_nsb = nsb <= kScanBlock ? (int)nsb : 0;
     if (!local_nsb) hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
@@ -690,11 +759,13 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
                        b.needed);
     const unsigned blocks = (unsigned)std::min<int64_t>((n * kGroup + 255) / 256, 8192);
     hipLaunchKernelGGL(k_stage, dim3(blocks, (unsigned)V), dim3(256), 0, st, p.rect, p.rec, n, tiles_x, tiles,
-                       p.visible, p.visible_start, soff, cnt, stp, stk, b.status);
+                       p.visible, p.visible_start, soff, cnt, stp, stk, chunks, n_chunks, max_chunks, b.status);
+    hipLaunchKernelGGL(k_stage_big, dim3(1024), dim3(256), 0, st, p.rect, p.rec, n, tiles_x, tiles, p.visible, soff,
+                       cnt, stp, stk, chunks, n_chunks, max_chunks, b.status);
   } else {
     // no surfels: empty lists, zero intersections
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)std::min<int64_t>((m + 256) / 256, 65535)), dim3(256), 0, st,
-                       cnt, m + 1, 0u);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)std::min<int64_t>((m + 257) / 256, 65535)), dim3(256), 0, st,
+                       cnt, m + 2, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, p.visible_start, (int64_t)V + 1, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, st, soff, (int64_t)1, 0u);
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(256), 0, st, b.needed, (int64_t)1, (int64_t)0);

@@ -14,7 +14,7 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
 
 // Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
-constexpr int kBinsortOffs = 10, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2, kCropOffs = 2;
+constexpr int kBinsortOffs = 11, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2, kCropOffs = 2;
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off);
 hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_x, int tiles_y, const cgv2_bins& b,
