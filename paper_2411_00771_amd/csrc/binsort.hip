@@ -2,7 +2,7 @@
 //
 // Instead of a global LSD radix sort over (view | tile | depth) keys, intersections are bucketed
 // by tile directly:
-//   surfel scan   one fused pass of three kernels (two up to kScanBlock chunks) over every (view,
+//   surfel scan   one fused pass of three kernels (two up to kSurfLocal chunks) over every (view,
 //                 surfel): the exclusive prefix sum of its tile count (from its rect) and the compaction
 //                 of the visible ones into per-view lists, plus the capacity check
 //   k_stage       groups of lanes per visible surfel: for each tile of its rect that the surfel's
@@ -66,6 +66,17 @@ __device__ __forceinline__ uint64_t wave_scan(uint64_t x) {
   return x;
 }
 
+// inclusive prefix sum over the 64 lanes of a wave (32-bit)
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+  const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+  for (unsigned d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
 constexpr int kScanWaves = kScanBlock / 64;
 
 // block-wide exclusive scan of kScanChunk values held kScanItems per thread (consecutive items per
@@ -122,27 +133,51 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ 
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// The surfel scan runs over chunks of kSurfChunk (view, surfel) entries, one 256-thread workgroup each;
+// a wave owns kSurfRows consecutive rows of 64 entries (coalesced loads), scans them with shuffles and
+// ballots, and only the wave totals go through LDS.
+constexpr int kSurfBlock = 256;
+constexpr int kSurfWaves = kSurfBlock / 64;
+constexpr int kSurfRows = 8;
+constexpr int kSurfChunk = kSurfBlock * kSurfRows;
+constexpr int kSurfLocal = 4 * kSurfBlock;  // up to this many chunks, each apply workgroup adds up those before it
+
 // pass 1 of the surfel scan: per-chunk sums of the tile counts and of the visible flags; the workgroups
-// also zero the nz tile counters (and the big-list count after them), which k_stage uses two launches later
-__global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __restrict__ rect, int64_t m,
+// also zero the nz tile counters (and the counts after them), which the staging uses two launches later
+__global__ __launch_bounds__(kSurfBlock) void k_surfel_sums(const uint16_t* __restrict__ rect, int64_t m,
                                                             uint64_t* __restrict__ sums_cnt,
                                                             uint64_t* __restrict__ sums_vis,
                                                             uint32_t* __restrict__ zero, int64_t nz) {
-  __shared__ uint64_t lds[2][kScanWaves];
-  for (int64_t z = (int64_t)blockIdx.x * kScanBlock + threadIdx.x; z < nz; z += (int64_t)gridDim.x * kScanBlock)
+  __shared__ uint64_t red[2][kSurfWaves];
+  for (int64_t z = (int64_t)blockIdx.x * kSurfBlock + threadIdx.x; z < nz; z += (int64_t)gridDim.x * kSurfBlock)
     zero[z] = 0u;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = (int64_t)blockIdx.x * kSurfChunk;
   uint64_t c = 0, f = 0;
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
+  for (int k = 0; k < kSurfRows; ++k) {
+    const int64_t idx = base + (int64_t)k * kSurfBlock + threadIdx.x;
     if (idx < m) {
       const uint32_t t = rect_count(rect + 4 * idx);
       c += t;
       f += t != 0u;
     }
   }
-  const uint64_t sc = block_sum(c, lds[0]), sf = block_sum(f, lds[1]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    c += shfl_xor64(c, o);
+    f += shfl_xor64(f, o);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = c;
+    red[1][w] = f;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    uint64_t sc = 0, sf = 0;
+    for (int q = 0; q < kSurfWaves; ++q) {
+      sc += red[0][q];
+      sf += red[1][q];
+    }
     sums_cnt[blockIdx.x] = sc;
     sums_vis[blockIdx.x] = sf;
   }
@@ -151,27 +186,39 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_sums(const uint16_t* __re
 // pass 3 of the surfel scan: soff[e] = first staged slot of (view, surfel) e, soff[m] = total;
 // visible[pos] = surfel id of every (view, surfel) with a non-empty rect in (view, id) order,
 // vstart[v] = first entry of view v, vstart[V] = total; the total is checked against the capacity.
-// local_nsb > 0 (at most kScanBlock chunks): the sums are pass 1's raw chunk sums and each workgroup
+// local_nsb > 0 (at most kSurfLocal chunks): the sums are pass 1's raw chunk sums and each workgroup
 // adds up those before it (pass 2 is skipped); 0: the sums are pass 2's scanned ones, totals its totals.
-__global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
+__global__ __launch_bounds__(kSurfBlock) void k_surfel_apply(
     const uint16_t* __restrict__ rect, int64_t m, int64_t n, const uint64_t* __restrict__ sums_cnt,
     const uint64_t* __restrict__ sums_vis, const uint64_t* __restrict__ totals, int local_nsb,
     uint32_t* __restrict__ soff, uint32_t* __restrict__ visible, uint32_t* __restrict__ vstart, int V,
     int64_t capacity, int32_t* __restrict__ status, int64_t* __restrict__ needed) {
-  __shared__ uint64_t lds[2 * kScanWaves];
-  __shared__ uint64_t red[4][kScanWaves];
+  __shared__ uint64_t red[4][kSurfWaves];
+  __shared__ uint32_t wt[2][kSurfWaves];
   __shared__ uint64_t carry[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (local_nsb > 0) {
-    const int j = threadIdx.x;
-    const uint64_t sc = j < local_nsb ? sums_cnt[j] : 0, sv = j < local_nsb ? sums_vis[j] : 0;
-    const bool before = j < (int)blockIdx.x;
-    // workgroup 0 has no chunk before it and alone needs the totals
-    if (blockIdx.x == 0) {
-      const uint64_t t0 = block_sum(sc, red[2]), t1 = block_sum(sv, red[3]);
-      if (j == 0) { carry[0] = 0; carry[1] = 0; carry[2] = t0; carry[3] = t1; }
-    } else {
-      const uint64_t c0 = block_sum(before ? sc : 0, red[0]), c1 = block_sum(before ? sv : 0, red[1]);
-      if (j == 0) { carry[0] = c0; carry[1] = c1; }
+    uint64_t r[4] = {0, 0, 0, 0};  // counts and flags before this chunk, then their totals
+    for (int j = threadIdx.x; j < local_nsb; j += kSurfBlock) {
+      const uint64_t sc = sums_cnt[j], sv = sums_vis[j];
+      if (j < (int)blockIdx.x) {
+        r[0] += sc;
+        r[1] += sv;
+      }
+      r[2] += sc;
+      r[3] += sv;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) r[k] += shfl_xor64(r[k], o);
+      if (lane == 0) red[k][w] = r[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      uint64_t t = 0;
+      for (int q = 0; q < kSurfWaves; ++q) t += red[threadIdx.x][q];
+      carry[threadIdx.x] = t;
     }
   } else if (threadIdx.x == 0) {
     carry[0] = sums_cnt[blockIdx.x];
@@ -179,27 +226,45 @@ __global__ __launch_bounds__(kScanBlock) void k_surfel_apply(
     carry[2] = totals[0];
     carry[3] = totals[1];
   }
-  __syncthreads();
-  const uint64_t carry_c = carry[0], carry_v = carry[1];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  uint64_t vc[kScanItems], vv[kScanItems];
-  uint32_t flag[kScanItems];
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t c = base + k < m ? rect_count(rect + 4 * (base + k)) : 0u;
-    vc[k] = c;
-    flag[k] = c != 0u;
-    vv[k] = flag[k];
+  // wave scans of the counts and of the visible flags over the wave's rows (32-bit: a chunk's counts
+  // stay far below 2^32)
+  const int64_t wbase = (int64_t)blockIdx.x * kSurfChunk + (int64_t)w * (64 * kSurfRows);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  uint32_t c[kSurfRows], ex[kSurfRows], fx[kSurfRows];
+  uint32_t cc = 0, fc = 0;
+#pragma unroll
+  for (int r = 0; r < kSurfRows; ++r) {
+    const int64_t idx = wbase + 64 * r + lane;
+    c[r] = idx < m ? rect_count(rect + 4 * idx) : 0u;
   }
-  block_scan(vc, lds);
-  block_scan(vv, lds);
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
+#pragma unroll
+  for (int r = 0; r < kSurfRows; ++r) {
+    const uint32_t inc = wave_scan_u32(c[r]);
+    ex[r] = cc + inc - c[r];
+    cc += __shfl(inc, 63, 64);
+    const unsigned long long fb = __ballot(c[r] != 0u);
+    fx[r] = fc + (uint32_t)__popcll(fb & lt);
+    fc += (uint32_t)__popcll(fb);
+  }
+  if (lane == 0) {
+    wt[0][w] = cc;
+    wt[1][w] = fc;
+  }
+  __syncthreads();
+  uint64_t oc = carry[0], ov = carry[1];
+  for (int q = 0; q < w; ++q) {
+    oc += wt[0][q];
+    ov += wt[1][q];
+  }
+#pragma unroll
+  for (int r = 0; r < kSurfRows; ++r) {
+    const int64_t e = wbase + 64 * r + lane;
     if (e >= m) continue;
-    const uint64_t c = vc[k] + carry_c;
-    soff[e] = (uint32_t)(c > 0xffffffffull ? 0xffffffffull : c);
-    const uint32_t pos = (uint32_t)(vv[k] + carry_v);
+    const uint64_t cs = oc + ex[r];
+    soff[e] = (uint32_t)(cs > 0xffffffffull ? 0xffffffffull : cs);
+    const uint32_t pos = (uint32_t)(ov + fx[r]);
     const int64_t i = e % n;
-    if (flag[k]) visible[pos] = (uint32_t)i;
+    if (c[r] != 0u) visible[pos] = (uint32_t)i;
     if (i == 0) vstart[e / n] = pos;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -597,15 +662,6 @@ __global__ __launch_bounds__(kOrdChunk) void k_order_place(const uint32_t* __res
 // registers (wave scans in k order, one LDS exchange of the 16 wave totals); the order takes LDS counts
 // per (wave, bucket), one exchange of the 16 x 64 counts into first slots, and a placing pass with
 // stable ranks from the lanes that share a bucket (same_bucket).
-__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
-  const unsigned lane = threadIdx.x & 63u;
-#pragma unroll
-  for (unsigned d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  return x;
-}
 
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* __restrict__ cnt, int m,
                                                                 uint32_t* __restrict__ ranges,
@@ -695,6 +751,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
 }  // namespace cgv2
 
 static int64_t scan_blocks(int64_t m) { return (m + cgv2::kScanChunk - 1) / cgv2::kScanChunk; }
+static int64_t surf_blocks(int64_t m) { return (m + cgv2::kSurfChunk - 1) / cgv2::kSurfChunk; }
 
 size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, size_t* off) {
   // off: [0] tile counters (u32, m) followed by the big-list and chunk-queue counts, [1] chunk sums of the surfel
@@ -703,7 +760,7 @@ size_t cgv2_binsort_ws_layout(int64_t capacity, int V, int tiles, int64_t n, siz
   //      capacity), [7] surfel offsets (u32, V n + 1), [8] chunk sums of the tile scan (u64)
   const int64_t m = (int64_t)V * tiles;
   const int64_t vn = (int64_t)V * n;
-  const int64_t nsb = scan_blocks(vn > 0 ? vn : 1);
+  const int64_t nsb = surf_blocks(vn > 0 ? vn : 1);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
   off[0] = take(4 * (size_t)(m + 2));
@@ -734,7 +791,7 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   char* w = (char*)ws;
   uint32_t* cnt = (uint32_t*)(w + off[0]);
   uint32_t* big_count = cnt + m;
-  const int64_t nsb = scan_blocks(vn > 0 ? vn : 1);
+  const int64_t nsb = surf_blocks(vn > 0 ? vn : 1);
   uint64_t* sums_cnt = (uint64_t*)(w + off[1]);
   uint64_t* sums_vis = sums_cnt + nsb + 1;
   uint32_t* big_list = (uint32_t*)(w + off[2]);
@@ -749,12 +806,12 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   if (n > 0) {
     // surfel offsets, visible lists (consumed by the staging here and by the reverse pass), total and
     // overflow check; the tile counters and the big-list count are zeroed on the way
-    hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, sums_cnt, sums_vis,
+    hipLaunchKernelGGL(k_surfel_sums, dim3((unsigned)nsb), dim3(kSurfBlock), 0, st, p.rect, vn, sums_cnt, sums_vis,
                        cnt, m + 2);
-    // up to kScanBlock chunks each apply workgroup adds up the chunk sums before it itself
-    const int local_nsb = nsb <= kScanBlock ? (int)nsb : 0;
+    // up to kSurfLocal chunks each apply workgroup adds up the chunk sums before it itself
+    const int local_nsb = nsb <= kSurfLocal ? (int)nsb : 0;
     if (!local_nsb) hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(kScanBlock), 0, st, sums_cnt, sums_vis, nsb, totals);
-    hipLaunchKernelGGL(k_surfel_apply, dim3((unsigned)nsb), dim3(kScanBlock), 0, st, p.rect, vn, n, sums_cnt,
+    hipLaunchKernelGGL(k_surfel_apply, dim3((unsigned)nsb), dim3(kSurfBlock), 0, st, p.rect, vn, n, sums_cnt,
                        sums_vis, totals, local_nsb, soff, p.visible, p.visible_start, V, b.capacity, b.status,
                        b.needed);
     const unsigned blocks = (unsigned)std::min<int64_t>((n * kGroup + 255) / 256, 8192);
