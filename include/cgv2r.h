@@ -299,7 +299,8 @@ int cgv2_densify_stats(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_
  * on one GPU shares that GPU's buffer, so calls that overlap on one GPU (other streams, other threads)
  * race: order them.  The buffer needs no clearing (each call writes what it reads).
  * Errors: CGV2_EINVAL as cgv2_densify_stats; CGV2_EWORKSPACE when cgv2_densify_workspace(n, V) exceeds
- * CGV2_NOALLOC_SCRATCH_BYTES (e.g. above about 40 M surfels at 8 views); CGV2_EUNSUPPORTED; CGV2_EHIP. */
+ * CGV2_NOALLOC_SCRATCH_BYTES (above about 75 M surfels at 8 views, 28 M at 32); CGV2_EUNSUPPORTED;
+ * CGV2_EHIP. */
 #define CGV2_NOALLOC_SCRATCH_BYTES (16u << 20)
 int cgv2_densify_stats_noalloc(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_grads* grads, int32_t V,
                                const cgv2_densify_params* prm, cgv2_densify_state* st, void* hip_stream);
