@@ -286,7 +286,10 @@ __global__ __launch_bounds__(kSurfBlock) void k_surfel_apply(
 constexpr int kGroup = 32;
 constexpr uint32_t kNoTile = 0xffffffffu;  // staged slot of a rect tile the surfel cannot reach
 constexpr uint32_t kChunkTiles = 4 * kGroup;
-constexpr uint32_t kFirstTiles = 2 * kChunkTiles;
+#ifndef CGV2_FIRST_CHUNKS
+#define CGV2_FIRST_CHUNKS 2
+#endif
+constexpr uint32_t kFirstTiles = CGV2_FIRST_CHUNKS * kChunkTiles;
 
 // One visible surfel of view v as the staging sees it.
 struct StageSurfel {
