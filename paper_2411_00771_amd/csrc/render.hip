@@ -132,17 +132,19 @@ __device__ __forceinline__ uint32_t stage_record(Stage& s, int lane, const float
 }
 
 // Per-surfel terms of a lane at its quadrant-0 pixel; pixel k sits at (xr0 + 8 (k & 1), yr0 + 8 (k >> 1))
-// relative to the projected centre.
+// relative to the projected centre (xr1 = xr0 + 8, yr1 = yr0 + 8).
 // (c1x, c1y, c2x, c2y, cwx, cwy) are the coefficients of x' and y' in P1, P2 and w: a pixel 8 columns or
 // rows further adds 8 times them (exact in FP32, so one FMA per term).
 struct LaneTerms {
-  float xr0, yr0, p1, p2, wb, c1x, c1y, c2x, c2y, cwx, cwy;
+  float xr0, yr0, xr1, yr1, p1, p2, wb, c1x, c1y, c2x, c2y, cwx, cwy;
 };
 
 __device__ __forceinline__ void lane_terms(float lx0, float ly0, const float4& q0, const float4& q1, const float4& q2,
                                            LaneTerms& t) {
   t.xr0 = lx0 - q0.x;
   t.yr0 = ly0 - q0.y;
+  t.xr1 = t.xr0 + 8.f;
+  t.yr1 = t.yr0 + 8.f;
   t.p1 = fmaf(q0.z, t.xr0, q0.w * t.yr0);
   t.p2 = fmaf(q1.x, t.xr0, q1.y * t.yr0);
   t.wb = fmaf(q1.w, t.xr0, fmaf(q2.x, t.yr0, q1.z));
@@ -164,8 +166,8 @@ struct Px {
 
 template <int k>
 __device__ __forceinline__ void eval_px(const LaneTerms& t, float lo, Px& e) {
-  e.xr = (k & 1) ? t.xr0 + 8.f : t.xr0;
-  e.yr = (k >> 1) ? t.yr0 + 8.f : t.yr0;
+  e.xr = (k & 1) ? t.xr1 : t.xr0;
+  e.yr = (k >> 1) ? t.yr1 : t.yr0;
   e.P1 = t.p1;
   e.P2 = t.p2;
   e.w = t.wb;
@@ -495,9 +497,7 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
   const float zc = q2.z, zw = q2.w;
   const float al = con ? e.alpha : 0.f;
   const float rom = __builtin_amdgcn_rcpf(1.f - al);
-  const float Tn = p.T;       // transmittance after this fragment
-  const float Ti = Tn * rom;  // ... and before it
-  const float wgt = al * Ti;
+  const float ar = al * rom;  // alpha / (1 - alpha)
   // upstream . (this fragment's attributes), for the total and the SSIM-only upstream
   float g = fmaf(p.GC[0], q3.x, fmaf(p.GC[1], q3.y, p.GC[2] * q3.z));
   const float gs = fmaf(p.GS[0], q3.x, fmaf(p.GS[1], q3.y, p.GS[2] * q3.z));
@@ -509,14 +509,19 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
     g = fmaf(p.GN[2], q4.z, g);
     g = fmaf(p.GD2, zf, g);
   }
+  // Tn = the transmittance after this fragment (its last use is the step back to the one in front, so
+  // the step writes in place)
+  const float Tn = p.T;
   // 2 (1 - alpha) dL/dalpha: what lies behind minus T in front times this fragment's attributes
   const float nA = fmaf(-Tn, g, p.sA);
   const float nS = fmaf(-Tn, gs, p.sS);
+  const float wgt = Tn * ar;  // alpha T_i
+  p.T = Tn * rom;             // T_i, in front of it
   p.sA = fmaf(wgt, g, p.sA);
   p.sS = fmaf(wgt, gs, p.sS);
   // d alpha / d alpha_raw / (1 - alpha): the 0.99 clamp blocks the path to o and rho; below it alpha is
   // alpha_raw, and a pixel that does not take the entry has al = 0
-  const float rA = e.araw > kAlphaMax ? 0.f : al * rom;
+  const float rA = e.araw > kAlphaMax ? 0.f : ar;
   acc[G_R] = fmaf(p.GC[0], wgt, acc[G_R]);
   acc[G_G] = fmaf(p.GC[1], wgt, acc[G_G]);
   acc[G_B] = fmaf(p.GC[2], wgt, acc[G_B]);
@@ -527,7 +532,6 @@ __device__ __forceinline__ void bwd_px(const LaneTerms& lt, const float4& q0, co
     acc[G_NZ] = fmaf(p.GN[2], wgt, acc[G_NZ]);
     dz = fmaf(p.GD, wgt, con && e_idx == p.med ? p.GM : 0.f);
   }
-  p.T = Ti;
   // -2 d rho of either upstream
   const float ndr = rA * nA;
   const float nds = rA * nS;
