@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_project_compact(cgv2_surfels_compact s,
 // being added to) is issued before its first store: the stores may alias the loaded arrays, so an
 // interleaved read-modify-write would cost one full memory round trip per element.
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd(cgv2_surfels s, CamPack cams,
+__global__ __launch_bounds__(64) void k_project_bwd(cgv2_surfels s, CamPack cams,
                                                       const uint32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ vstart,
                                                       RecGrads rg, cgv2_grads gr) {
@@ -556,7 +556,9 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   const int64_t n = s.n;
-  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  // one wave per workgroup: the visible surfels (a few percent of n) then spread over every CU instead
+  // of filling the first few with four-wave workgroups
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 63) / 64, 16384);
   // g_view rows are overwritten: zero for surfels outside each view's list
   const int64_t rows = (int64_t)cams.count * 2 * n;
   const unsigned fill_blocks = (unsigned)std::min<int64_t>((rows + 255) / 256, 65535);
@@ -573,10 +575,10 @@ hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& c
     const uint32_t* list = p.visible;
     const uint32_t* cnt = p.visible_start + v;
     switch (s.sh_degree) {
-      case 0: hipLaunchKernelGGL(cgv2::k_project_bwd<0>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
-      case 1: hipLaunchKernelGGL(cgv2::k_project_bwd<1>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
-      case 2: hipLaunchKernelGGL(cgv2::k_project_bwd<2>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
-      default: hipLaunchKernelGGL(cgv2::k_project_bwd<3>, dim3(blocks), dim3(256), 0, st, s, one, list, cnt, rg, g); break;
+      case 0: hipLaunchKernelGGL(cgv2::k_project_bwd<0>, dim3(blocks), dim3(64), 0, st, s, one, list, cnt, rg, g); break;
+      case 1: hipLaunchKernelGGL(cgv2::k_project_bwd<1>, dim3(blocks), dim3(64), 0, st, s, one, list, cnt, rg, g); break;
+      case 2: hipLaunchKernelGGL(cgv2::k_project_bwd<2>, dim3(blocks), dim3(64), 0, st, s, one, list, cnt, rg, g); break;
+      default: hipLaunchKernelGGL(cgv2::k_project_bwd<3>, dim3(blocks), dim3(64), 0, st, s, one, list, cnt, rg, g); break;
     }
   }
   return hipGetLastError();
