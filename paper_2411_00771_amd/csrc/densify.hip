@@ -138,24 +138,29 @@ __global__ __launch_bounds__(kDBlock) void k_densify(cgv2_surfels s, const uint8
   if (threadIdx.x < kCounters) cpart[(int64_t)blockIdx.x * kCounters + threadIdx.x] = cnt_s[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kDBlock) void k_count_final(const uint32_t* __restrict__ cpart, int nblocks,
+constexpr int kCBlock = 1024;
+
+__global__ __launch_bounds__(kCBlock) void k_count_final(const uint32_t* __restrict__ cpart, int nblocks,
                                                          uint32_t* __restrict__ counters) {
-  __shared__ uint32_t red[kCounters][kDBlock];
+  __shared__ uint32_t red[kCounters][kCBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t a[kCounters] = {0, 0, 0, 0, 0, 0};
-#pragma unroll 8
-  for (int b = threadIdx.x; b < nblocks; b += kDBlock)
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblocks; b += kCBlock)
 #pragma unroll
     for (int c = 0; c < kCounters; ++c) a[c] += cpart[(int64_t)b * kCounters + c];
 #pragma unroll
-  for (int c = 0; c < kCounters; ++c) red[c][threadIdx.x] = a[c];
-  __syncthreads();
-  for (int off = kDBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off)
+  for (int c = 0; c < kCounters; ++c) {
 #pragma unroll
-      for (int c = 0; c < kCounters; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) a[c] += __shfl_xor(a[c], o, 64);
+    if (lane == 0) red[c][w] = a[c];
   }
-  if (threadIdx.x < kCounters) counters[threadIdx.x] += red[threadIdx.x][0];
+  __syncthreads();
+  if (threadIdx.x < kCounters) {
+    uint32_t t = 0;
+    for (int q = 0; q < kCBlock / 64; ++q) t += red[threadIdx.x][q];
+    counters[threadIdx.x] += t;
+  }
 }
 
 }  // namespace cgv2
@@ -189,7 +194,7 @@ hipError_t cgv2_launch_densify(const cgv2_surfels& s, const cgv2_proj& p, const 
     const int nbd = (int)((n + cgv2::kDBlock - 1) / cgv2::kDBlock);
     hipLaunchKernelGGL(cgv2::k_densify, dim3((unsigned)nbd), dim3(cgv2::kDBlock), 0, stream, s, p.flags, p.radius,
                        g.g_view_total, g.g_view_ssim, V, scale_ws, prm, st, cpart);
-    hipLaunchKernelGGL(cgv2::k_count_final, dim3(1), dim3(cgv2::kDBlock), 0, stream, cpart, nbd, st.counters);
+    hipLaunchKernelGGL(cgv2::k_count_final, dim3(1), dim3(cgv2::kCBlock), 0, stream, cpart, nbd, st.counters);
   }
   return hipGetLastError();
 }
