@@ -304,10 +304,15 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& a, Stage& s, u
   const float lx0 = (float)lx + 0.5f, ly0 = (float)ly + 0.5f;
   uint8_t* qmask = kMask ? a.img.qmask : nullptr;
   uint32_t qlive = live_quadrants<kSub>(f);
+  // the list ids of the next chunk are loaded one chunk ahead: staging then waits on one load round trip
+  // (the records) instead of two
+  uint32_t nid = start + lane < end ? a.ids[start + lane] : 0u;
   for (uint32_t base = start; base < end && qlive != 0; base += 64) {
     const uint32_t idx = base + lane;
+    const uint32_t id = nid;
     QuadBits qb;
-    qb.from_lanes(idx < end ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, nullptr, 0) : 0u);
+    qb.from_lanes(idx < end ? stage_record(s, lane, a.rec, vn, a.n, id, ox, oy, nullptr, 0) : 0u);
+    nid = idx + 64u < end ? a.ids[idx + 64u] : 0u;
     __syncthreads();
     const int cnt = (int)min(64u, end - base);
     int reached = cnt;  // entries of this chunk the wave evaluated
@@ -639,11 +644,17 @@ __device__ __forceinline__ void render_bwd_tile(const BwdArgs& A, Stage& s, uint
   const int slot = reduce16_index(lane);
   const float sc = slot_scale(slot);
 
+  // the list ids of the next (lower) chunk are loaded one chunk ahead, as in the forward
+  uint32_t nlo = hi - start > 64u ? hi - 64u : start;
+  uint32_t nid = nlo + lane < hi ? a.ids[nlo + lane] : 0u;
   for (uint32_t top = hi; top > start;) {
-    const uint32_t lo = top - start > 64u ? top - 64u : start;
+    const uint32_t lo = nlo;
     const uint32_t idx = lo + lane;
+    const uint32_t id = nid;
     QuadBits qb;
-    qb.from_lanes(idx < top ? stage_record(s, lane, a.rec, vn, a.n, a.ids[idx], ox, oy, a.img.qmask, idx) : 0u);
+    qb.from_lanes(idx < top ? stage_record(s, lane, a.rec, vn, a.n, id, ox, oy, a.img.qmask, idx) : 0u);
+    nlo = lo - start > 64u ? lo - 64u : start;
+    nid = nlo + lane < lo ? a.ids[nlo + lane] : 0u;
     __syncthreads();
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
       const uint32_t e_idx = lo + (uint32_t)j;
