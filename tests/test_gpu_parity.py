@@ -485,3 +485,32 @@ def test_property_scenes_against_oracle(cuda, seed):
     ranges, gids = fetch_bins(eng)
     compare_lists(ranges, gids, po, cam, P=fetch_proj(eng), max_excluded=4)
     compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=0.05)
+
+
+def test_large_rects_staged_in_chunks_bit_exact(cuda):
+    """Surfels whose rect covers far more than the 256 tiles a staging group takes itself (the rest goes
+    through the 128-tile chunk queue), among ordinary ones: the lists equal the oracle's entry for entry
+    and the images match it."""
+    rng = np.random.default_rng(31)
+    sc = scenes.tiny_scene(31, 3000)
+    cam = scenes.tiny_camera(480, 400)
+    # 24 wide surfels close to the camera, some elongated, at random orientations
+    k = 24
+    sc.mean[:, :k] = np.stack([rng.uniform(-0.6, 0.6, k), rng.uniform(-0.5, 0.5, k),
+                               rng.uniform(1.5, 2.4, k)]).astype(np.float32)
+    sc.log_scale[0, :k] = np.log(rng.uniform(0.5, 1.2, k)).astype(np.float32)
+    sc.log_scale[1, :k] = np.log(rng.uniform(0.05, 1.2, k)).astype(np.float32)
+    po = oracle.project(sc, cam)
+    tr = po["tile_rect"].astype(np.int64)
+    tiles = (tr[:, 2] - tr[:, 0]) * (tr[:, 3] - tr[:, 1])
+    assert (tiles > 256).sum() >= 10 and tiles.max() > 2 * 256  # several rects need queued chunks
+    eng, _, _ = gpu_forward(sc, [cam], capacity=1 << 19)
+    P = fetch_proj(eng)
+    ranges, ids = fetch_bins(eng)
+    r = compare_lists(ranges, ids, po, cam, P=P, max_excluded=8)
+    assert r["surfels"] <= 2
+    assert int(eng.needed.item()) == r["rect_total"]
+    assert int(eng.status.item()) == 0
+    off, oids, _ = oracle.bin_view(po, cam)
+    io = oracle.render(po, cam, off, oids)
+    compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=5e-3)
