@@ -14,9 +14,9 @@
 //                 kScanChunk tiles of at most kMaxViews views, k_tile_scan_order also computes the
 //                 launch order in the same workgroup (the multi-workgroup order kernels otherwise)
 //   k_place       one thread per staged slot: keys[ranges[tile] + rank] = key (no atomics)
-//   k_sort_small  one workgroup per tile: LDS bitonic sort of lists up to kSmall entries
-//   k_sort_big    lists up to kBig entries in 128 KB of LDS; longer lists are sorted in kBig chunks
-//                 and merged in global memory by rank (binary search)
+//   k_sort_wave   one wave per tile: bitonic sort of lists up to kWaveSort entries in registers
+//   k_sort_big    longer lists, up to kBig entries in 128 KB of LDS; longer still are sorted in kBig
+//                 chunks and merged in global memory by rank (binary search)
 // (depth bits, id) is unique within a tile, so the order in which the atomics hand out ranks does not
 // matter: the result is deterministic and bit-exact.  HBM traffic is about 16 B staged + 16 B read +
 // 8 B placed + 8 B read + 4 B written per intersection.
@@ -27,7 +27,6 @@
 
 namespace cgv2 {
 
-constexpr int kSmall = 2048;   // entries sorted by k_sort_small (16 KB of LDS)
 constexpr int kBig = 16384;    // entries sorted in LDS by k_sort_big (128 KB)
 constexpr int kScanBlock = 1024;
 constexpr int kScanItems = 8;  // elements per thread per scan block
@@ -485,29 +484,121 @@ __device__ __forceinline__ int next_pow2(int x) {
   return p;
 }
 
-__global__ __launch_bounds__(256) void k_sort_small(const uint32_t* __restrict__ ranges, int num_tiles,
-                                                    const uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
-                                                    uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count,
-                                                    const int32_t* __restrict__ status) {
-  __shared__ uint64_t s[kSmall];
-  const int t = blockIdx.x;
+// ---- per-tile sort of up to kWaveSort keys in one wave's registers ----------------------------------
+// A bitonic network over 64 E keys, E per lane in blocked order (key x = E lane + e).  Steps whose partner
+// distance j is below E pair two registers of a lane; the others pair register e of lanes l and l ^ j / E,
+// exchanged with DPP (distances 1, 2, 4, 8) or the gfx950 row-swap instructions (16, 32), so the sort
+// touches neither LDS nor a barrier.  A compare-exchange keeps the minimum where the lane holds the
+// lower index of an ascending pair or the upper one of a descending pair.
+constexpr int kWaveSort = 1024;  // longest list sorted in registers (E = 16)
+
+// value of lane l ^ D for D = 1, 2, 4, 8 (DPP within rows of 16)
+template <int D>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
+  const int i = (int)x;
+  if constexpr (D == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, i, 0xB1, 0xf, 0xf, false);   // [1,0,3,2]
+  if constexpr (D == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, i, 0x4E, 0xf, 0xf, false);   // [2,3,0,1]
+  if constexpr (D == 4) {  // l ^ 7 (row_half_mirror), then ^ 3 (quad_perm [3,2,1,0])
+    const int h = __builtin_amdgcn_update_dpp(0, i, 0x141, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, h, 0x1B, 0xf, 0xf, false);
+  }
+  if constexpr (D == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, i, 0x128, 0xf, 0xf, false);  // row_ror:8
+}
+
+// register e of lanes l and l ^ D: keep the smaller key where keep_min, else the larger
+template <int D>
+__device__ __forceinline__ void cx_lanes(uint64_t& v, bool keep_min) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  uint64_t a, b;  // the two keys of the pair (which one is this lane's does not matter)
+  if constexpr (D <= 8) {
+    a = v;
+    b = ((uint64_t)lane_xor<D>(hi) << 32) | lane_xor<D>(lo);
+  } else {
+    // a row swap of a register with itself leaves this lane's key in one result and its partner's in
+    // the other
+    const auto rl = D == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = D == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = ((uint64_t)rh[0] << 32) | rl[0];
+    b = ((uint64_t)rh[1] << 32) | rl[1];
+  }
+  v = ((a < b) == keep_min) ? a : b;
+}
+
+// registers x (lower index) and y of one lane, ascending or descending
+__device__ __forceinline__ void cx_regs(uint64_t& x, uint64_t& y, bool asc) {
+  const bool c = (x < y) == asc;
+  const uint64_t p = c ? x : y, q = c ? y : x;
+  x = p;
+  y = q;
+}
+
+template <int E, int K, int J>
+__device__ __forceinline__ void bitonic_step(uint64_t (&v)[E], unsigned lane) {
+  if constexpr (J >= E) {
+    // K >= 2 J >= 2 E: the direction follows bit K / E of the lane (all ascending in the last merge)
+    const bool asc = K >= 64 * E || (lane & (unsigned)(K / E)) == 0u;
+    const bool keep_min = ((lane & (unsigned)(J / E)) == 0u) == asc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) cx_lanes<J / E>(v[e], keep_min);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e & J) continue;
+      const bool asc = K < E ? (e & K) == 0 : (K >= 64 * E || (lane & (unsigned)(K / E)) == 0u);
+      cx_regs(v[e], v[e | J], asc);
+    }
+  }
+  if constexpr (J > 1) bitonic_step<E, K, J / 2>(v, lane);
+}
+
+template <int E, int K = 2>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[E], unsigned lane) {
+  bitonic_step<E, K, K / 2>(v, lane);
+  if constexpr (K < 64 * E) wave_bitonic<E, 2 * K>(v, lane);
+}
+
+// keys[a, a + len) sorted by one wave (len <= 64 E), ids written in order; the tail is padded with the
+// largest key
+template <int E>
+__device__ __forceinline__ void sort_list_wave(const uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                               uint32_t a, int len, unsigned lane) {
+  uint64_t v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = E * (int)lane + e;
+    v[e] = x < len ? keys[a + x] : ~0ull;
+  }
+  wave_bitonic<E>(v, lane);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = E * (int)lane + e;
+    if (x < len) ids[a + x] = (uint32_t)v[e];
+  }
+}
+
+// One wave per tile: lists up to kWaveSort entries are sorted in registers with the smallest E that
+// holds them; longer ones go to big_list for k_sort_big.
+__global__ __launch_bounds__(256) void k_sort_wave(const uint32_t* __restrict__ ranges, int num_tiles,
+                                                   const uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                   uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count,
+                                                   const int32_t* __restrict__ status) {
+  const int t = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
   if (t >= num_tiles || *status != 0) return;
+  const unsigned lane = threadIdx.x & 63u;
   const uint32_t a = ranges[t], b = ranges[t + 1];
   const int len = (int)(b - a);
   if (len == 0) return;
-  if (len > kSmall) {
-    if (threadIdx.x == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)t;
+  if (len > kWaveSort) {
+    if (lane == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)t;
     return;
   }
-  if (len == 1) {
-    if (threadIdx.x == 0) ids[a] = (uint32_t)keys[a];
-    return;
-  }
-  const int p = next_pow2(len);
-  for (int k = threadIdx.x; k < p; k += 256) s[k] = k < len ? keys[a + k] : ~0ull;
-  __syncthreads();
-  lds_bitonic<256>(s, p);
-  for (int k = threadIdx.x; k < len; k += 256) ids[a + k] = (uint32_t)s[k];
+  if (len <= 64) sort_list_wave<1>(keys, ids, a, len, lane);
+  else if (len <= 128) sort_list_wave<2>(keys, ids, a, len, lane);
+  else if (len <= 256) sort_list_wave<4>(keys, ids, a, len, lane);
+  else if (len <= 512) sort_list_wave<8>(keys, ids, a, len, lane);
+  else sort_list_wave<16>(keys, ids, a, len, lane);
 }
 
 // rank of key x in sorted run r[0..len): number of elements < x
@@ -846,8 +937,8 @@ hipError_t cgv2_launch_bin_sort(const cgv2_proj& p, int64_t n, int V, int tiles_
   // only known on the device, so the grid follows the capacity and the surplus threads exit at once
   const unsigned place_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((b.capacity + 255) / 256, 1), 16384);
   hipLaunchKernelGGL(k_place, dim3(place_blocks), dim3(256), 0, st, soff + vn, stp, stk, b.ranges, keys, b.status);
-  hipLaunchKernelGGL(k_sort_small, dim3((unsigned)m), dim3(256), 0, st, b.ranges, (int)m, keys, b.ids, big_list,
-                     big_count, b.status);
+  hipLaunchKernelGGL(k_sort_wave, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, b.ranges, (int)m, keys, b.ids,
+                     big_list, big_count, b.status);
   hipLaunchKernelGGL(k_sort_big, dim3(256), dim3(1024), 0, st, b.ranges, keys, stk, b.ids, big_list, big_count,
                      b.status);
   if (b.order && !fused_order) {
