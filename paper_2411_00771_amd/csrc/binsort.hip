@@ -65,16 +65,26 @@ __device__ __forceinline__ uint64_t wave_scan(uint64_t x) {
   return x;
 }
 
-// inclusive prefix sum over the 64 lanes of a wave (32-bit)
+// inclusive prefix sum over the 64 lanes of a wave (32-bit) with DPP row shifts and row broadcasts
+// only: each row of 16 lanes scans itself, then rows 1 and 3 add the total of the row before, then
+// rows 2 and 3 that of rows 0-1 (lanes a shift or broadcast does not reach receive 0)
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, false);
+}
+
 __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
-  const unsigned lane = threadIdx.x & 63u;
-#pragma unroll
-  for (unsigned d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  x += dpp_u32<0x111>(x);       // row_shr:1
+  x += dpp_u32<0x112>(x);       // row_shr:2
+  x += dpp_u32<0x114>(x);       // row_shr:4
+  x += dpp_u32<0x118>(x);       // row_shr:8
+  x += dpp_u32<0x142, 0xa>(x);  // row_bcast:15
+  x += dpp_u32<0x143, 0xc>(x);  // row_bcast:31
   return x;
 }
+
+// the value of lane 63 (a wave total after wave_scan_u32)
+__device__ __forceinline__ uint32_t lane63(uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, 63); }
 
 constexpr int kScanWaves = kScanBlock / 64;
 
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(kSurfBlock) void k_surfel_apply(
   for (int r = 0; r < kSurfRows; ++r) {
     const uint32_t inc = wave_scan_u32(c[r]);
     ex[r] = cc + inc - c[r];
-    cc += __shfl(inc, 63, 64);
+    cc += lane63(inc);
     const unsigned long long fb = __ballot(c[r] != 0u);
     fx[r] = fc + (uint32_t)__popcll(fb & lt);
     fc += (uint32_t)__popcll(fb);
@@ -780,7 +790,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t inc = wave_scan_u32(c[k]);
     ex[k] = carry + inc - c[k];
-    carry += __shfl(inc, 63, 64);
+    carry += lane63(inc);
   }
   if (lane == 0) wtot[w] = carry;
   const unsigned long long lt = (1ull << lane) - 1ull;
@@ -813,13 +823,8 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
     uint32_t tot = 0;
     for (int q = 0; q < kScanWaves; ++q) tot += wc[q][t];
     // buckets in descending order: bucket t starts after the tiles of the buckets above it
-    uint32_t x = tot;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_down(x, d, 64);
-      if (t + d < 64) x += y;
-    }
-    uint32_t run = x - tot;
+    const uint32_t inc = wave_scan_u32(tot);
+    uint32_t run = lane63(inc) - inc;
     for (int q = 0; q < kScanWaves; ++q) {
       const uint32_t v = wc[q][t];
       wc[q][t] = run;
