@@ -808,15 +808,12 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan_order(const uint32_t* 
     if (64 * k < per && i < i1) ranges[i] = off + ex[k];
   }
   if (t == 0) ranges[m] = total;
-  // counts per (wave, bucket): the first lane of each bucket present in 64 tiles adds their number
-  // (one wave, LDS in program order)
+  // counts per (wave, bucket), by LDS atomics that return nothing (no wait between the rows)
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (i0 + 64 * k >= i1) break;
     const int i = i0 + 64 * k + lane;
-    const int bk = i < i1 ? order_bucket(c[k]) : -1;
-    const unsigned long long same = same_bucket(bk);
-    if (bk >= 0 && (same & lt) == 0) wc[w][bk] += (uint32_t)__popcll(same);
+    if (i < i1) atomicAdd(&wc[w][order_bucket(c[k])], 1u);
   }
   __syncthreads();
   if (t < kOrdBuckets) {

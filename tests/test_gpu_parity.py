@@ -434,11 +434,12 @@ def test_long_tile_lists_sorted_bit_exact(cuda):
 
 
 def test_tile_lists_of_every_sort_class_bit_exact(cuda):
-    """Tiles holding exactly L entries for L around every power of two of the per-tile sorts (one 256-thread
-    workgroup up to 2048 entries, one 1024-thread workgroup above), with many exact depth ties: the lists
-    equal the oracle's entry for entry."""
-    lengths = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700, 1024, 1500, 2048, 2049, 3000]
-    cam = scenes.tiny_camera(80, 64)
+    """Tiles holding exactly L entries for L around every power of two of the per-tile sorts (one wave's
+    registers with 1, 2, 4, 8 or 16 keys per lane up to 1024 entries, one 1024-thread workgroup in LDS
+    above), with many exact depth ties: the lists equal the oracle's entry for entry."""
+    lengths = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700, 1024, 1025, 1500, 2048, 2049,
+               3000]
+    cam = scenes.tiny_camera(96, 64)
     tx = (cam.width + 15) // 16
     rng = np.random.default_rng(23)
     f = float(np.float32(cam.fx))
