@@ -19,7 +19,7 @@ F_VISIBLE, F_NEAR, F_OPACITY, F_BEHIND, F_NONFINITE, F_LOWPASS = 1, 2, 4, 8, 16,
 
 EXPORTS = ["cgv2_project", "cgv2_project_compact", "cgv2_bin_sort_workspace", "cgv2_bin_sort", "cgv2_render_fwd", "cgv2_loss_workspace",
            "cgv2_loss", "cgv2_render_bwd_workspace", "cgv2_render_bwd", "cgv2_render_bwd_records",
-           "cgv2_project_bwd", "cgv2_densify_workspace",
+           "cgv2_project_bwd", "cgv2_zero_grads", "cgv2_densify_workspace",
            "cgv2_densify_stats", "cgv2_densify_stats_noalloc", "cgv2_render_count", "cgv2_contribution_workspace", "cgv2_contribution",
            "cgv2_trim_workspace", "cgv2_trim_mask", "cgv2_densify_plan_workspace", "cgv2_densify_plan",
            "cgv2_densify_apply", "cgv2_densify_gather", "cgv2_visibility_workspace", "cgv2_visibility_count",
@@ -131,6 +131,7 @@ def lib():
                                                    P]),
         "cgv2_project_bwd": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Camera), i32,
                                             P, sz, ctypes.POINTER(Grads), P]),
+        "cgv2_zero_grads": (ctypes.c_int, [ctypes.POINTER(Grads), i64, i32, P]),
         "cgv2_densify_workspace": (sz, [i64, i32]),
         "cgv2_densify_stats": (ctypes.c_int, [ctypes.POINTER(Surfels), ctypes.POINTER(Proj), ctypes.POINTER(Grads), i32,
                                               ctypes.POINTER(DensifyParams), ctypes.POINTER(DensifyState), P, sz, P]),

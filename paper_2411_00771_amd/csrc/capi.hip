@@ -262,6 +262,16 @@ int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_ca
   return bwd_project(s, proj, cams, V, workspace, g, (hipStream_t)stream);
 }
 
+int cgv2_zero_grads(const cgv2_grads* g, int64_t n, int32_t sh_degree, void* stream) {
+  if (!g || n < 0 || sh_degree < 0 || sh_degree > 3) return CGV2_EINVAL;
+  if (n > 0 && (!g->d_mean || !g->d_log_scale || !g->d_quat || !g->d_opacity_logit || !g->d_sh)) return CGV2_EINVAL;
+  const float* ps[5] = {g->d_mean, g->d_log_scale, g->d_quat, g->d_opacity_logit, g->d_sh};
+  for (const float* p : ps)
+    if ((uintptr_t)p & 3u) return CGV2_EINVAL;
+  if (const int dv = device_check()) return dv;
+  return hip_status(cgv2_launch_zero_grads(*g, n, sh_degree, (hipStream_t)stream));
+}
+
 size_t cgv2_densify_workspace(int64_t n, int32_t V) {
   if (n < 0 || V < 1) return 0;
   size_t off[kDensifyOffs];

@@ -12,6 +12,7 @@ hipError_t cgv2_launch_project_compact(const cgv2_surfels_compact& s, const cgv2
                                       hipStream_t st);
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st);
+hipError_t cgv2_launch_zero_grads(const cgv2_grads& g, int64_t n, int sh_degree, hipStream_t st);
 
 // Workspace layouts: each fills off[0 .. k*Offs) with byte offsets and returns the total size.
 constexpr int kBinsortOffs = 11, kLossOffs = 2, kDensifyOffs = 2, kTrimOffs = 3, kActionOffs = 2, kCropOffs = 2;

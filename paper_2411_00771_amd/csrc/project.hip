@@ -552,6 +552,49 @@ hipError_t cgv2_launch_project(const cgv2_surfels& s, const cgv2::CamPack& cams,
   return hipGetLastError();
 }
 
+namespace cgv2 {
+
+// Zeroing of the parameter gradients: one grid walks the five arrays with 16-byte stores (the floats
+// before an array's first 16-byte boundary and after its last one singly), about eight per thread.
+struct ZeroList {
+  float* p[5];
+  int64_t count[5];
+};
+
+__global__ __launch_bounds__(256) void k_zero_grads(ZeroList z) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll 1
+  for (int a = 0; a < 5; ++a) {
+    float* p = z.p[a];
+    const int64_t c = z.count[a];
+    const int64_t head = std::min<int64_t>(c, (int64_t)(((16u - ((uintptr_t)p & 15u)) & 15u) / 4u));
+    if (tid < head) p[tid] = 0.f;
+    float4* q = (float4*)(p + head);
+    const int64_t n4 = (c - head) / 4;
+    for (int64_t i = tid; i < n4; i += nt) q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t t0 = head + 4 * n4;
+    if (tid < c - t0) p[t0 + tid] = 0.f;
+  }
+}
+
+}  // namespace cgv2
+
+hipError_t cgv2_launch_zero_grads(const cgv2_grads& g, int64_t n, int sh_degree, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t K = (int64_t)(sh_degree + 1) * (sh_degree + 1);
+  cgv2::ZeroList z;
+  float* p[5] = {g.d_mean, g.d_log_scale, g.d_quat, g.d_opacity_logit, g.d_sh};
+  const int64_t c[5] = {3 * n, 2 * n, 4 * n, n, 3 * K * n};
+  for (int a = 0; a < 5; ++a) {
+    z.p[a] = p[a];
+    z.count[a] = c[a];
+  }
+  const int64_t total = (3 * K + 10) * n;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total / 4 + 2047) / 2048, 4096));
+  hipLaunchKernelGGL(cgv2::k_zero_grads, dim3(blocks), dim3(256), 0, st, z);
+  return hipGetLastError();
+}
+
 hipError_t cgv2_launch_project_bwd(const cgv2_surfels& s, const cgv2::CamPack& cams, const cgv2_proj& p,
                                    const cgv2::RecGrads& rg, const cgv2_grads& g, hipStream_t st) {
   if (s.n == 0) return hipSuccess;

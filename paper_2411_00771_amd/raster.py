@@ -75,13 +75,16 @@ class Grads:
         self.mean, self.log_scale, self.quat, self.opacity_logit, self.sh = (z.mean, z.log_scale, z.quat,
                                                                            z.opacity_logit, z.sh)
         n = params.n
+        self.n, self.sh_degree = n, params.sh_degree
         dev = params.mean.device
         self.g_view_total = torch.zeros((views, 2, n), device=dev)
         self.g_view_ssim = torch.zeros((views, 2, n), device=dev)
 
     def zero_(self):
-        for t in (self.mean, self.log_scale, self.quat, self.opacity_logit, self.sh):
-            t.zero_()
+        """cgv2_zero_grads on the current stream (the parameter gradients; the view-space ones are
+        overwritten by each backward)."""
+        check(_lib.lib().cgv2_zero_grads(ctypes.byref(self.struct()), self.n, self.sh_degree, _stream()),
+              "cgv2_zero_grads")
 
     def struct(self) -> _lib.Grads:
         g = _lib.Grads()

@@ -97,6 +97,15 @@ def test_argument_validation_returns_einval():
                              ctypes.byref(up), ctypes.byref(g), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
     assert L.cgv2_render_bwd_records(ctypes.byref(p), ctypes.byref(okbins), cams, 1, 10, ctypes.byref(img),
                                      ctypes.byref(up), ctypes.c_void_p(256), 1 << 30, None) == EINVAL
+    # zeroing: no gradients, a missing or misaligned array, n < 0, an SH degree outside 0-3
+    assert L.cgv2_zero_grads(None, 10, 3, None) == EINVAL
+    assert L.cgv2_zero_grads(ctypes.byref(g), 10, 3, None) == EINVAL
+    ga = _lib.Grads(*[ctypes.c_void_p(256 * (k + 1)) for k in range(7)])
+    assert L.cgv2_zero_grads(ctypes.byref(ga), -1, 3, None) == EINVAL
+    assert L.cgv2_zero_grads(ctypes.byref(ga), 10, 4, None) == EINVAL
+    gm = _lib.Grads(*([ctypes.c_void_p(256 * (k + 1)) for k in range(4)] + [ctypes.c_void_p(258)] +
+                      [ctypes.c_void_p(256)] * 2))
+    assert L.cgv2_zero_grads(ctypes.byref(gm), 10, 3, None) == EINVAL
     # parameter gradients missing
     assert L.cgv2_project_bwd(ctypes.byref(s), ctypes.byref(p), cams, 1, ctypes.c_void_p(256), 1 << 30,
                               ctypes.byref(g), None) == EINVAL

@@ -515,3 +515,33 @@ def test_large_rects_staged_in_chunks_bit_exact(cuda):
     off, oids, _ = oracle.bin_view(po, cam)
     io = oracle.render(po, cam, off, oids)
     compare_images(fetch_img(eng), io, io["margin"], max_fragile_frac=5e-3)
+
+
+def test_zero_grads_clears_exactly_the_parameter_gradients(cuda):
+    """cgv2_zero_grads: the five parameter-gradient arrays zeroed whatever their alignment and length (arrays
+    placed at odd float offsets, lengths not multiples of 4, for SH degrees 0-3), nothing before or after
+    them touched, the view-space gradients left as they were."""
+    import ctypes
+    import torch
+    from paper_2411_00771_amd import _lib
+    L = _lib.lib()
+    for deg, n in ((0, 1), (1, 7), (2, 1001), (3, 65537)):
+        K = (deg + 1) ** 2
+        counts = [3 * n, 2 * n, 4 * n, n, 3 * K * n]
+        total = sum(c + 9 for c in counts) + 8
+        buf = torch.full((total,), 7.0, device="cuda")
+        offs, o = [], 1
+        for c in counts:
+            offs.append(o)
+            o += c + 9
+        gv = torch.full((2, 2, n), 5.0, device="cuda")
+        g = _lib.Grads(*[ctypes.c_void_p(buf.data_ptr() + 4 * a) for a in offs],
+                       ctypes.c_void_p(gv.data_ptr()), ctypes.c_void_p(gv[1].data_ptr()))
+        assert L.cgv2_zero_grads(ctypes.byref(g), n, deg, None) == 0
+        torch.cuda.synchronize()
+        want = torch.full((total,), 7.0, device="cuda")
+        for a, c in zip(offs, counts):
+            want[a:a + c] = 0.0
+        assert torch.equal(buf, want), (deg, n)
+        assert bool((gv == 5.0).all())
+
