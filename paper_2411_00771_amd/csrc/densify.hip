@@ -1,7 +1,7 @@
 // Densification statistics of CityGaussianV2 Sec. 3.2: the decomposed-gradient densification
 // factor of Eq. 2 and the elongation filter.
 //
-// k_dgd_partial  per view, per block of 1024 surfels: sums of |g_total| and |g_ssim| over the
+// k_dgd_partial  per view, per block of 512 surfels: sums of |g_total| and |g_ssim| over the
 //                visible surfels, tree-reduced in FP64 in a fixed order
 // k_dgd_final    one workgroup reduces each view's block partials in a fixed order into
 //                scale_v = max(omega a_tot / a_ssim, 1) (deterministic)
@@ -15,7 +15,7 @@
 namespace cgv2 {
 
 constexpr int kDBlock = 256;
-constexpr int kDItems = 4;  // surfels per thread in k_dgd_partial
+constexpr int kDItems = 2;  // surfels per thread in k_dgd_partial
 
 __global__ __launch_bounds__(kDBlock) void k_dgd_partial(const uint8_t* __restrict__ flags,
                                                          const float* __restrict__ gt, const float* __restrict__ gs,
