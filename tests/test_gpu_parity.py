@@ -545,3 +545,56 @@ def test_zero_grads_clears_exactly_the_parameter_gradients(cuda):
         assert torch.equal(buf, want), (deg, n)
         assert bool((gv == 5.0).all())
 
+
+def test_zeroing_on_a_second_stream_matches_in_line(cuda):
+    """The benchmark's step order: the parameter gradients zeroed on a second stream that waits for an event
+    after the previous step's chain and is waited for before this step's chain; three steps on three views
+    give the same gradients as the same steps with the zeroing in line (each step's chain adds into freshly
+    zeroed gradients either way), up to the rounding order of the reverse pass's float atomics."""
+    import torch
+    from paper_2411_00771_amd import raster
+    w = scenes.workload(0)
+    sc = w["scene"]
+    cams = [scenes.tiny_camera(128, 128, dist=d) for d in (2.8, 3.0, 3.3)]
+    params = raster.Params.from_scene(sc)
+    eng = raster.Engine(sc.n, 128, 128, 1, capacity=1 << 16)
+    tgt = torch.from_numpy(np.ascontiguousarray(w["targets"][0], np.float32)).cuda()[None]
+
+    def run(overlap):
+        g = raster.Grads(params, 1)
+        out = []
+        zs = torch.cuda.Stream()
+        free, zeroed = torch.cuda.Event(), torch.cuda.Event()
+        free.record()
+        for cam in cams:
+            cs = eng.cams([cam])
+            if overlap:
+                zs.wait_event(free)
+                with torch.cuda.stream(zs):
+                    g.zero_()
+                    zeroed.record(zs)
+            else:
+                g.zero_()
+            eng.status.zero_()
+            eng.project(params, cs)
+            eng.bin_sort(cs)
+            eng.render(cs)
+            eng.loss(tgt)
+            eng.backward_records(cs, d_rgb=eng.d_img, d_rgb_ssim=eng.d_img_ssim)
+            if overlap:
+                torch.cuda.current_stream().wait_event(zeroed)
+            eng.project_backward(params, cs, g)
+            if overlap:
+                free.record()
+            out.append(torch.cat([t.reshape(-1) for t in (g.mean, g.log_scale, g.quat, g.opacity_logit, g.sh)]))
+            out[-1] = out[-1].clone()
+        torch.cuda.synchronize()
+        assert eng.status.item() == 0
+        return out
+
+    a, b = run(False), run(True)
+    for x, y in zip(a, b):
+        # the reverse pass adds with float atomics, so compare to the atomics' rounding, not bit for bit
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-9)
+        assert bool((x != 0).any())
+
