@@ -71,18 +71,34 @@ struct Stage {
   float4 q[64][5];
 };
 
-// Bit j of qb[k]: staged entry j reaches quadrant k (one ballot per quadrant of the lanes' masks).
+// The 4-bit quadrant masks of the 64 staged entries as nibbles in scalar registers: entry j's mask is
+// bits 4 (j % 16) .. 4 (j % 16) + 3 of w[j / 16].  Built with one OR reduction over each row of 16 lanes
+// (DPP row shifts) and four lane reads per half; reading one entry's mask is then a shift and a mask.
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_or_in(uint32_t v) {
+  return v | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xf, 0xf, false);
+}
 struct QuadBits {
-  uint64_t qb[4];
+  uint64_t w[4];
   __device__ __forceinline__ void from_lanes(uint32_t m) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t sh = 4u * (lane & 7u);
+    uint32_t lo = (lane & 8u) ? 0u : (m & 0xfu) << sh, hi = (lane & 8u) ? (m & 0xfu) << sh : 0u;
+    lo = dpp_or_in<0x111>(lo);  // row_shr:1
+    hi = dpp_or_in<0x111>(hi);
+    lo = dpp_or_in<0x112>(lo);  // row_shr:2
+    hi = dpp_or_in<0x112>(hi);
+    lo = dpp_or_in<0x114>(lo);  // row_shr:4
+    hi = dpp_or_in<0x114>(hi);
+    lo = dpp_or_in<0x118>(lo);  // row_shr:8: lane 15 of each row holds the row's OR
+    hi = dpp_or_in<0x118>(hi);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) qb[k] = __ballot((m >> k) & 1u);
+    for (int r = 0; r < 4; ++r)
+      w[r] = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, 16 * r + 15) << 32 |
+             (uint32_t)__builtin_amdgcn_readlane((int)lo, 16 * r + 15);
   }
-  // the 4-bit quadrant mask of entry j
-  __device__ __forceinline__ uint32_t at(int j) const {
-    return (uint32_t)((qb[0] >> j) & 1u) | (uint32_t)((qb[1] >> j) & 1u) << 1 |
-           (uint32_t)((qb[2] >> j) & 1u) << 2 | (uint32_t)((qb[3] >> j) & 1u) << 3;
-  }
+  // the nibbles of entries 16 i .. 16 i + 15 (i wave-uniform)
+  __device__ __forceinline__ uint64_t word(int i) const { return i == 0 ? w[0] : i == 1 ? w[1] : i == 2 ? w[2] : w[3]; }
 };
 
 // Quadrants (bits of 'm') in which some pixel sample can reach alpha >= 1/255 (reach_setup / reach_cell).
@@ -318,13 +334,15 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& a, Stage& s, u
     int reached = cnt;  // entries of this chunk the wave evaluated
     // bit j of cq[k]: quadrant k had a taking pixel at entry base + j (scalar registers)
     uint64_t cq[4] = {0, 0, 0, 0};
+    uint64_t cur = qb.w[0];  // entry j's nibble in bits 0-3
     for (int j = 0; j < cnt; ++j) {
       if (kCount) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if ((kSub >> k) & 1u) n_eval += f[k].T > 0.f ? 1u : 0u;
       }
-      const uint32_t m = qb.at(j) & qlive;
+      const uint32_t m = (uint32_t)cur & 0xfu & qlive;
+      cur >>= 4;
       if (m != 0) {
         const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
         LaneTerms lt;
@@ -361,6 +379,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& a, Stage& s, u
           reached = j + 1;
           break;
         }
+        cur = qb.word((j + 1) >> 4);
       }
     }
     // entries past 'reached' lie beyond every pixel's 'last': the reverse pass never reads them
@@ -652,15 +671,23 @@ __device__ __forceinline__ void render_bwd_tile(const BwdArgs& A, Stage& s, uint
     const uint32_t idx = lo + lane;
     const uint32_t id = nid;
     QuadBits qb;
-    qb.from_lanes(idx < top ? stage_record(s, lane, a.rec, vn, a.n, id, ox, oy, a.img.qmask, idx) : 0u);
+    {
+      // the subset's quadrants, each only below its walk bound
+      uint32_t allow = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) allow |= (((kSub >> k) & 1u) && idx < qhi[k] ? 1u : 0u) << k;
+      qb.from_lanes(idx < top ? stage_record(s, lane, a.rec, vn, a.n, id, ox, oy, a.img.qmask, idx) & allow : 0u);
+    }
     nlo = lo - start > 64u ? lo - 64u : start;
     nid = nlo + lane < lo ? a.ids[nlo + lane] : 0u;
     __syncthreads();
+    const int j0 = (int)(top - lo) - 1;
+    uint64_t cur = qb.word(j0 >> 4) << (4 * (15 - (j0 & 15)));  // entry j's nibble in bits 60-63
     for (int j = (int)(top - lo) - 1; j >= 0; --j) {
       const uint32_t e_idx = lo + (uint32_t)j;
-      uint32_t m = qb.at(j) & kSub;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) m &= e_idx < qhi[k] ? 0xfu : ~(1u << k);
+      if ((j & 15) == 15) cur = qb.word(j >> 4);
+      const uint32_t m = (uint32_t)(cur >> 60);  // quadrant bits, kSub and the quadrants' walk bounds applied
+      cur <<= 4;
       if (m == 0) continue;
       const float4 q0 = s.q[j][0], q1 = s.q[j][1], q2 = s.q[j][2], q3 = s.q[j][3], q4 = s.q[j][4];
       LaneTerms lt;
