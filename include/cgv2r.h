@@ -281,7 +281,8 @@ int cgv2_project_bwd(const cgv2_surfels* s, const cgv2_proj* proj, const cgv2_ca
 /* Zeroes the parameter gradients of grads (d_mean, d_log_scale, d_quat, d_opacity_logit and d_sh of n
  * surfels of SH degree sh_degree, 0-3, with the layouts above; the view-space gradients are left as they
  * are, cgv2_project_bwd overwrites them) before the views of a step add into them, in one launch.
- * Errors: CGV2_EINVAL (a null or misaligned array for n > 0), CGV2_EHIP. */
+ * Unlike the other calls it also takes arrays that are only 4-byte aligned.
+ * Errors: CGV2_EINVAL (for n > 0, an array that is null or not 4-byte aligned), CGV2_EHIP. */
 int cgv2_zero_grads(const cgv2_grads* grads, int64_t n, int32_t sh_degree, void* hip_stream);
 
 /* Workspace bytes for cgv2_densify_stats. */
